@@ -1,0 +1,212 @@
+/*
+ * gsm.h — C ABI of an MI355X (gfx950) subgraph matcher.
+ *
+ * The library enumerates or counts every embedding of a small connected query
+ * graph Q in a large undirected data graph G stored as CSR: injective maps f
+ * from query vertices to data vertices that keep vertex labels and map every
+ * query edge onto a data edge (non-induced).  Automorphic images are distinct
+ * embeddings.  This is the matching problem of the GSM paper (Wang and Owens,
+ * "Fast Gunrock Subgraph Matching (GSM) on GPUs", arXiv 2003.01527), Sec. 3.2
+ * and Alg. 1: inputs Q and G, outputs the count and the listing.
+ *
+ * The method is the paper's breadth-first filtering-and-verification:
+ *   - a host pre-computation orders the query vertices (Alg. 1
+ *     PreCompute_on_CPUs);
+ *   - candidates are filtered on the GPU by label, degree and neighbourhood
+ *     encoding, with refinement rounds (Alg. 1 Filter_candidate_set);
+ *   - partial matches are expanded level by level: gather the neighbours of
+ *     an already-matched vertex, verify every edge back to the matched
+ *     vertices plus injectivity, and compact the survivors (Alg. 1
+ *     Verify_Constraints: Advance, Compute, Write_to_Partial);
+ *   - each expansion is cut into chunks that fit a device memory budget, so
+ *     memory stays bounded however many partial matches there are (the
+ *     paper's stated memory goal, Sec. 1 and Sec. 5).
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns a gsm_status.  On an error the out-parameters are
+ *     left untouched (except as noted for GSM_E_TRUNCATED) and
+ *     gsm_last_error() gives a message for the calling thread.
+ *   - Create calls deep-copy their inputs; the caller may free them on
+ *     return.  The library owns the handles it returns; destroy(NULL) is a
+ *     no-op.
+ *   - Pointers are host pointers unless a flag or option says "device".
+ *   - Calls on one graph handle are serialised internally (one workspace per
+ *     handle); distinct handles may be used from distinct threads.
+ *   - Rows are q int32 columns in query-vertex-id order.  Row order is
+ *     unspecified (work is distributed with atomics).
+ */
+#ifndef GSM_H
+#define GSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsm_graph *gsm_graph_t;
+typedef struct gsm_query *gsm_query_t;
+typedef struct gsm_server *gsm_server_t;
+
+typedef enum gsm_status {
+  GSM_OK = 0,
+  GSM_E_INVALID_ARG = 1, /* NULL handle or pointer, size out of range */
+  GSM_E_BAD_GRAPH = 2,   /* CSR fails validation */
+  GSM_E_BAD_QUERY = 3,   /* query disconnected, not simple, or too large */
+  GSM_E_OOM = 4,         /* device or host allocation failed */
+  GSM_E_BUDGET = 5,      /* memory budget below one row of some level */
+  GSM_E_DEVICE = 6,      /* a HIP call failed */
+  GSM_E_TRUNCATED = 7,   /* output buffer smaller than the count */
+  GSM_E_CANCELLED = 8,   /* the emit callback asked to stop */
+  GSM_E_UNSUPPORTED = 9, /* option not available in this build */
+  GSM_E_TIMEOUT = 10     /* server wait timed out */
+} gsm_status;
+
+#define GSM_MAX_QUERY_VERTICES 16
+
+/* ------------------------------------------------------------------ graph -- */
+
+#define GSM_GRAPH_VALIDATE 1u    /* check the CSR (see gsm_graph_create) */
+#define GSM_GRAPH_DEVICE_PTRS 2u /* row_ptr, col, labels are device pointers */
+
+/*
+ * Uploads a data graph.  The graph must be simple and undirected: each edge
+ * stored in both rows, rows strictly ascending, no self-loops (the paper takes
+ * undirected CSR input with no preprocessing, Sec. 2 and Sec. 3.3).
+ *   n        number of vertices, 0 <= n < 2^31
+ *   row_ptr  n+1 offsets, row_ptr[0] = 0, non-decreasing
+ *   col      row_ptr[n] neighbour ids in [0, n)
+ *   labels   n vertex labels >= 0, or NULL for an unlabelled graph (all 0)
+ *   flags    GSM_GRAPH_VALIDATE checks every property above (O(m log d) on
+ *            the host) and returns GSM_E_BAD_GRAPH on a violation;
+ *            GSM_GRAPH_DEVICE_PTRS takes device pointers (copied device-side;
+ *            validation then copies them to the host first).
+ * Also computes per-vertex degree and neighbourhood encoding on the device.
+ */
+gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                            const int32_t *labels, uint32_t flags, gsm_graph_t *out);
+void gsm_graph_destroy(gsm_graph_t g);
+
+/* n, CSR entries (2m), largest label, largest degree. Any out pointer may be NULL. */
+gsm_status gsm_graph_info(gsm_graph_t g, int64_t *n, int64_t *nnz, int32_t *max_label,
+                          int64_t *max_degree);
+
+/* ------------------------------------------------------------------ query -- */
+
+/*
+ * A connected, simple query graph with 1 <= q <= 16 vertices (Sec. 3.2).
+ *   edges   ne pairs (a, b), 0 <= a, b < q, a != b, no duplicates
+ *   labels  q labels >= 0, or NULL (all 0)
+ * GSM_E_BAD_QUERY when disconnected, not simple, or q out of range.
+ */
+gsm_status gsm_query_create(int32_t q, int32_t ne, const int32_t *edges, const int32_t *labels,
+                            gsm_query_t *out);
+void gsm_query_destroy(gsm_query_t qh);
+
+/*
+ * The host pre-computation of Alg. 1 (PreCompute_on_CPUs, Sec. 3.2): query
+ * vertices in visiting order, greedily by larger d_M (edges to vertices
+ * already ordered), smaller P_f (label frequency times the fraction of data
+ * vertices of at least the query vertex's degree), larger degree, smaller id.
+ *   order[i]     query vertex at position i
+ *   parent[i]    position of its spanning-tree parent (earliest earlier
+ *                neighbour), -1 at position 0
+ *   backmask[i]  bit j set when position j < i is adjacent to position i
+ */
+typedef struct gsm_plan_info {
+  int32_t q;
+  int32_t order[GSM_MAX_QUERY_VERTICES];
+  int32_t parent[GSM_MAX_QUERY_VERTICES];
+  uint32_t backmask[GSM_MAX_QUERY_VERTICES];
+} gsm_plan_info;
+
+gsm_status gsm_query_plan(gsm_graph_t g, gsm_query_t qh, gsm_plan_info *out);
+
+/* ------------------------------------------------------------------ match -- */
+
+/* Per-call counters.  Level i is the expansion from i matched vertices to i+1. */
+typedef struct gsm_stats {
+  uint32_t struct_size;
+  int32_t q;
+  uint64_t candidates_root;             /* rows of the first frontier */
+  uint64_t rows[GSM_MAX_QUERY_VERTICES];  /* rows[i]: partial matches with i+1 vertices */
+  uint64_t pairs[GSM_MAX_QUERY_VERTICES]; /* pairs[i]: (row, neighbour) pairs tested at level i */
+  uint64_t chunks[GSM_MAX_QUERY_VERTICES];
+  uint64_t probes;                      /* binary-search steps of the back-edge checks */
+  uint64_t alg_bytes;                   /* algorithmic bytes of the expansion launches */
+  uint64_t filter_bytes;                /* algorithmic bytes of the filter */
+  uint64_t expand_launches;             /* expansion kernel launches */
+  double ms_expand;                     /* summed expansion kernel time (HIP events; needs profile) */
+  double ms_total;                      /* host wall time of the call */
+} gsm_stats;
+
+/* Emit callback: receives nrows rows, valid only during the call: host memory,
+ * or device memory written on the match's stream when rows_on_device is also
+ * set (the stream is synchronised before the call).  Return 0 to continue,
+ * non-zero to stop (gsm_match then returns GSM_E_CANCELLED). */
+typedef int (*gsm_emit_fn)(void *ctx, const int32_t *rows, uint64_t nrows, int32_t q);
+
+typedef struct gsm_match_opts {
+  uint32_t struct_size;         /* sizeof(gsm_match_opts) */
+  uint64_t memory_budget_bytes; /* device bytes for frontiers; 0 = 4 GiB */
+  int32_t filter_rounds;        /* refinement rounds (Alg. 1 Filter+Compute), default 1 */
+  int32_t use_degree;           /* degree test, default 1 */
+  int32_t use_ne;               /* neighbourhood-encoding test, default 1 */
+  int32_t rows_on_device;       /* the rows argument of gsm_match is device memory */
+  void *hip_stream;             /* hipStream_t to run on; NULL = the null stream */
+  int32_t root_qvertex;         /* -1 = no slice; else keep f(root) with */
+  uint32_t root_mod, root_rem;  /*   splitmix64(f(root)) % root_mod == root_rem */
+  gsm_emit_fn emit;             /* optional row sink, called once per output chunk */
+  void *emit_ctx;
+  gsm_stats *stats;             /* optional */
+  int32_t tile_items;           /* pairs per thread per tile: 1, 2, 4, 8 (0 = auto) */
+  int32_t wg_size;              /* threads per workgroup: 128, 256, 512 (0 = auto) */
+  int32_t profile;              /* time each expansion launch with HIP events into stats */
+} gsm_match_opts;
+
+/* Fills defaults (struct_size set, budget 0, rounds 1, degree and NE on, no slice). */
+void gsm_match_opts_init(gsm_match_opts *o);
+
+/*
+ * Candidate sets of the filtering stage (Alg. 1 Filter_candidate_set):
+ * cmask[v] bit u is set when data vertex v is a candidate of query vertex u:
+ * labels equal, deg(v) >= deg(u), NE(v) >= NE(u) where NE(x) sums (label+1)
+ * over x's neighbours, then filter_rounds refinement rounds recomputing deg
+ * and NE over neighbours that are still candidates of some query vertex.
+ *   cmask  host array of n uint16 (query-vertex-id bits)
+ */
+gsm_status gsm_filter(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, uint16_t *cmask);
+
+/*
+ * Counts, and optionally lists, the embeddings of qh in g.
+ *   opts          NULL = defaults
+ *   count         out: exact number of embeddings (also on GSM_E_TRUNCATED)
+ *   rows          NULL = count only; else rows_cap rows of q int32 (host,
+ *                 or device when opts->rows_on_device)
+ *   rows_written  out, may be NULL: rows stored = min(count, rows_cap)
+ * Returns GSM_E_TRUNCATED (count still exact) when count > rows_cap.
+ * With opts->emit set, rows are handed to the callback chunk by chunk
+ * instead (rows may be NULL).
+ */
+gsm_status gsm_match(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, uint64_t *count,
+                     int32_t *rows, uint64_t rows_cap, uint64_t *rows_written);
+
+/*
+ * Counts the embeddings of nq queries on one graph in one pass of
+ * level-synchronous batched launches (queries of different sizes and levels
+ * share every launch; sizes stay on the device, so the whole pass is one
+ * captured HIP graph).  counts[k] equals gsm_match's count for qs[k].
+ */
+gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query_t *qs,
+                           const gsm_match_opts *opts, uint64_t *counts);
+
+/* ----------------------------------------------------------------- errors -- */
+
+const char *gsm_status_str(gsm_status s);
+const char *gsm_last_error(void); /* thread-local; "" when none */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSM_H */

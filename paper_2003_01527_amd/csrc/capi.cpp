@@ -1,0 +1,326 @@
+// C ABI: errors, graph and query handles, the visiting-order query.
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "gsm_internal.h"
+
+namespace gsm {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+void DevBuf::reserve(size_t want) {
+  if (want <= bytes && ptr) return;
+  if (ptr) (void)hipDeviceSynchronize();  // no pending kernel may still use the old buffer
+  release();
+  if (want == 0) return;
+  size_t b = (want + 255) & ~size_t(255);
+  hipError_t e = hipMalloc(&ptr, b);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    (void)hipGetLastError();
+    throw Error{GSM_E_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed"};
+  }
+  bytes = b;
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+Workspace::Workspace() {
+  counters.reserve(64 * sizeof(uint64_t));
+  scan_scratch.reserve(scan_scratch_elems() * sizeof(uint64_t));
+  GSM_HIP(hipHostMalloc((void **)&h_counters, 64 * sizeof(uint64_t), hipHostMallocDefault));
+  std::memset(h_counters, 0, 64 * sizeof(uint64_t));
+}
+
+Workspace::~Workspace() {
+  if (h_counters) (void)hipHostFree(h_counters);
+  for (auto &e : events) (void)hipEventDestroy(e);
+}
+
+}  // namespace gsm
+
+using gsm::Error;
+
+#define GSM_API_BEGIN try {
+#define GSM_API_END                                        \
+  }                                                        \
+  catch (const Error &e) {                                 \
+    gsm::set_error(e.msg);                                 \
+    return e.status;                                       \
+  }                                                        \
+  catch (const std::bad_alloc &) {                         \
+    gsm::set_error("host allocation failed");              \
+    return GSM_E_OOM;                                      \
+  }                                                        \
+  catch (const std::exception &e) {                        \
+    gsm::set_error(e.what());                              \
+    return GSM_E_DEVICE;                                   \
+  }
+
+extern "C" {
+
+const char *gsm_status_str(gsm_status s) {
+  switch (s) {
+    case GSM_OK: return "ok";
+    case GSM_E_INVALID_ARG: return "invalid argument";
+    case GSM_E_BAD_GRAPH: return "bad graph";
+    case GSM_E_BAD_QUERY: return "bad query";
+    case GSM_E_OOM: return "out of memory";
+    case GSM_E_BUDGET: return "memory budget too small";
+    case GSM_E_DEVICE: return "device error";
+    case GSM_E_TRUNCATED: return "output truncated";
+    case GSM_E_CANCELLED: return "cancelled";
+    case GSM_E_UNSUPPORTED: return "unsupported";
+    case GSM_E_TIMEOUT: return "timeout";
+  }
+  return "unknown status";
+}
+
+const char *gsm_last_error(void) { return gsm::g_last_error.c_str(); }
+
+static gsm_status validate_csr(int64_t n, const int64_t *rp, const int32_t *col) {
+  if (rp[0] != 0) {
+    gsm::set_error("row_ptr[0] != 0");
+    return GSM_E_BAD_GRAPH;
+  }
+  for (int64_t v = 0; v < n; ++v) {
+    if (rp[v + 1] < rp[v]) {
+      gsm::set_error("row_ptr decreases at vertex " + std::to_string(v));
+      return GSM_E_BAD_GRAPH;
+    }
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k) {
+      const int32_t w = col[k];
+      if (w < 0 || w >= n) {
+        gsm::set_error("neighbour id out of range in row " + std::to_string(v));
+        return GSM_E_BAD_GRAPH;
+      }
+      if (w == v) {
+        gsm::set_error("self-loop at vertex " + std::to_string(v));
+        return GSM_E_BAD_GRAPH;
+      }
+      if (k > rp[v] && col[k - 1] >= w) {
+        gsm::set_error("row " + std::to_string(v) + " not strictly ascending");
+        return GSM_E_BAD_GRAPH;
+      }
+    }
+  }
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k) {
+      const int32_t w = col[k];
+      if (!std::binary_search(col + rp[w], col + rp[w + 1], (int32_t)v)) {
+        gsm::set_error("edge " + std::to_string(v) + "-" + std::to_string(w) + " not symmetric");
+        return GSM_E_BAD_GRAPH;
+      }
+    }
+  return GSM_OK;
+}
+
+gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                            const int32_t *labels, uint32_t flags, gsm_graph_t *out) {
+  GSM_API_BEGIN
+  if (!out || n < 0 || n >= (int64_t(1) << 31) || !row_ptr) {
+    gsm::set_error("gsm_graph_create: invalid arguments");
+    return GSM_E_INVALID_ARG;
+  }
+  const bool dev = flags & GSM_GRAPH_DEVICE_PTRS;
+  // host views of the inputs (downloaded when the caller handed device pointers)
+  std::vector<int64_t> h_rp_store;
+  std::vector<int32_t> h_col_store, h_lab_store;
+  const int64_t *h_rp = row_ptr;
+  const int32_t *h_col = col, *h_lab = labels;
+  int64_t nnz;
+  if (dev) {
+    h_rp_store.resize(n + 1);
+    GSM_HIP(hipMemcpy(h_rp_store.data(), row_ptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    h_rp = h_rp_store.data();
+    nnz = h_rp[n];
+    if (nnz < 0) {
+      gsm::set_error("row_ptr[n] < 0");
+      return GSM_E_BAD_GRAPH;
+    }
+    if (flags & GSM_GRAPH_VALIDATE) {
+      h_col_store.resize(nnz);
+      if (nnz)
+        GSM_HIP(hipMemcpy(h_col_store.data(), col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+      h_col = h_col_store.data();
+    }
+    if (labels) {
+      h_lab_store.resize(n);
+      if (n) GSM_HIP(hipMemcpy(h_lab_store.data(), labels, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+      h_lab = h_lab_store.data();
+    }
+  } else {
+    nnz = row_ptr[n];
+  }
+  if (nnz > 0 && !col) {
+    gsm::set_error("gsm_graph_create: col is NULL");
+    return GSM_E_INVALID_ARG;
+  }
+  if (flags & GSM_GRAPH_VALIDATE) {
+    gsm_status st = validate_csr(n, h_rp, h_col);
+    if (st != GSM_OK) return st;
+  }
+  int32_t max_label = 0;
+  if (h_lab)
+    for (int64_t v = 0; v < n; ++v) {
+      if (h_lab[v] < 0) {
+        gsm::set_error("negative label at vertex " + std::to_string(v));
+        return GSM_E_BAD_GRAPH;
+      }
+      max_label = std::max(max_label, h_lab[v]);
+    }
+  auto g = new gsm_graph();
+  try {
+    g->n = n;
+    g->nnz = nnz;
+    g->labelled = labels != nullptr;
+    g->max_label = max_label;
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    GSM_HIP(hipMalloc((void **)&g->rp, (n + 1) * sizeof(int64_t)));
+    GSM_HIP(hipMemcpy(g->rp, row_ptr, (n + 1) * sizeof(int64_t), kind));
+    GSM_HIP(hipMalloc((void **)&g->col, std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+    if (nnz) GSM_HIP(hipMemcpy(g->col, col, nnz * sizeof(int32_t), kind));
+    GSM_HIP(hipMalloc((void **)&g->deg, std::max<int64_t>(n, 1) * sizeof(uint32_t)));
+    if (labels) {
+      GSM_HIP(hipMalloc((void **)&g->lab, std::max<int64_t>(n, 1) * sizeof(int32_t)));
+      if (n) GSM_HIP(hipMemcpy(g->lab, labels, n * sizeof(int32_t), kind));
+      GSM_HIP(hipMalloc((void **)&g->ne0, std::max<int64_t>(n, 1) * sizeof(uint64_t)));
+    }
+    gsm::launch_graph_stats(*g, nullptr);
+    // planner statistics and the high-degree vertex list
+    g->label_count.assign((size_t)max_label + 1, 0);
+    int64_t maxd = 0;
+    std::vector<int32_t> heavy;
+    for (int64_t v = 0; v < n; ++v) {
+      const int64_t d = h_rp[v + 1] - h_rp[v];
+      maxd = std::max(maxd, d);
+      if (d > gsm::kHeavyDegree) heavy.push_back((int32_t)v);
+      g->label_count[h_lab ? h_lab[v] : 0]++;
+    }
+    g->max_degree = maxd;
+    g->deg_ge.assign((size_t)maxd + 2, 0);
+    for (int64_t v = 0; v < n; ++v) g->deg_ge[h_rp[v + 1] - h_rp[v]]++;
+    for (int64_t d = maxd; d >= 0; --d) g->deg_ge[d] += g->deg_ge[d + 1];
+    g->nheavy = (int64_t)heavy.size();
+    if (!heavy.empty()) {
+      GSM_HIP(hipMalloc((void **)&g->heavy, heavy.size() * sizeof(int32_t)));
+      GSM_HIP(hipMemcpy(g->heavy, heavy.data(), heavy.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    GSM_HIP(hipDeviceSynchronize());
+  } catch (...) {
+    gsm_graph_destroy(g);
+    throw;
+  }
+  *out = g;
+  return GSM_OK;
+  GSM_API_END
+}
+
+void gsm_graph_destroy(gsm_graph_t g) {
+  if (!g) return;
+  (void)hipDeviceSynchronize();
+  delete g->ws;
+  (void)hipFree(g->rp);
+  (void)hipFree(g->col);
+  (void)hipFree(g->lab);
+  (void)hipFree(g->deg);
+  (void)hipFree(g->ne0);
+  (void)hipFree(g->heavy);
+  delete g;
+}
+
+gsm_status gsm_graph_info(gsm_graph_t g, int64_t *n, int64_t *nnz, int32_t *max_label,
+                          int64_t *max_degree) {
+  if (!g) {
+    gsm::set_error("gsm_graph_info: NULL graph");
+    return GSM_E_INVALID_ARG;
+  }
+  if (n) *n = g->n;
+  if (nnz) *nnz = g->nnz;
+  if (max_label) *max_label = g->max_label;
+  if (max_degree) *max_degree = g->max_degree;
+  return GSM_OK;
+}
+
+gsm_status gsm_query_create(int32_t q, int32_t ne, const int32_t *edges, const int32_t *labels,
+                            gsm_query_t *out) {
+  GSM_API_BEGIN
+  if (!out || ne < 0 || (ne > 0 && !edges)) {
+    gsm::set_error("gsm_query_create: invalid arguments");
+    return GSM_E_INVALID_ARG;
+  }
+  if (q < 1 || q > gsm::kMaxQ) {
+    gsm::set_error("query size must be in [1, 16]");
+    return GSM_E_BAD_QUERY;
+  }
+  auto qh = std::make_unique<gsm_query>();
+  qh->q = q;
+  for (int e = 0; e < ne; ++e) {
+    const int32_t a = edges[2 * e], b = edges[2 * e + 1];
+    if (a < 0 || b < 0 || a >= q || b >= q || a == b) {
+      gsm::set_error("query edge " + std::to_string(e) + " out of range or a self-loop");
+      return GSM_E_BAD_QUERY;
+    }
+    if ((qh->adj[a] >> b) & 1) {
+      gsm::set_error("duplicate query edge " + std::to_string(a) + "-" + std::to_string(b));
+      return GSM_E_BAD_QUERY;
+    }
+    qh->adj[a] |= 1u << b;
+    qh->adj[b] |= 1u << a;
+    qh->edges.push_back(a);
+    qh->edges.push_back(b);
+  }
+  for (int u = 0; u < q; ++u) {
+    qh->label[u] = labels ? labels[u] : 0;
+    if (qh->label[u] < 0) {
+      gsm::set_error("negative query label");
+      return GSM_E_BAD_QUERY;
+    }
+  }
+  uint32_t seen = 1, frontier = 1;
+  while (frontier) {
+    uint32_t nxt = 0;
+    for (int u = 0; u < q; ++u)
+      if ((frontier >> u) & 1) nxt |= qh->adj[u];
+    frontier = nxt & ~seen;
+    seen |= nxt;
+  }
+  if (seen != ((q == 32) ? 0xffffffffu : ((1u << q) - 1u))) {
+    gsm::set_error("query graph is not connected");
+    return GSM_E_BAD_QUERY;
+  }
+  *out = qh.release();
+  return GSM_OK;
+  GSM_API_END
+}
+
+void gsm_query_destroy(gsm_query_t qh) { delete qh; }
+
+gsm_status gsm_query_plan(gsm_graph_t g, gsm_query_t qh, gsm_plan_info *out) {
+  GSM_API_BEGIN
+  if (!g || !qh || !out) {
+    gsm::set_error("gsm_query_plan: NULL argument");
+    return GSM_E_INVALID_ARG;
+  }
+  const gsm::Plan p = gsm::make_plan(*g, *qh);
+  std::memset(out, 0, sizeof(*out));
+  out->q = p.q;
+  for (int i = 0; i < p.q; ++i) {
+    out->order[i] = p.order[i];
+    out->parent[i] = p.parent[i];
+    out->backmask[i] = p.backmask[i];
+  }
+  return GSM_OK;
+  GSM_API_END
+}
+
+}  // extern "C"

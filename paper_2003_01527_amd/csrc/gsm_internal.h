@@ -1,0 +1,191 @@
+// Internal types shared by the host driver and the HIP kernels of libgsm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gsm.h"
+
+namespace gsm {
+
+constexpr int kMaxQ = GSM_MAX_QUERY_VERTICES;
+
+// ------------------------------------------------------------------ errors --
+
+void set_error(const std::string &msg);
+
+struct Error {
+  gsm_status status;
+  std::string msg;
+};
+
+#define GSM_HIP(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      throw ::gsm::Error{GSM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// ------------------------------------------------------------ device buffer --
+
+// Device allocation that grows on demand and is reused across calls.
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  void reserve(size_t want);  // keeps no contents
+  void release();
+  template <typename T>
+  T *as() const { return static_cast<T *>(ptr); }
+  ~DevBuf() { release(); }
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+};
+
+// ------------------------------------------------------------------- graph --
+
+struct Workspace;
+
+}  // namespace gsm
+
+struct gsm_graph {
+  int64_t n = 0;
+  int64_t nnz = 0;
+  bool labelled = false;
+  int32_t max_label = 0;
+  int64_t max_degree = 0;
+  // device CSR and per-vertex data
+  int64_t *rp = nullptr;     // n+1
+  int32_t *col = nullptr;    // nnz
+  int32_t *lab = nullptr;    // n, or null when unlabelled
+  uint32_t *deg = nullptr;   // n
+  uint64_t *ne0 = nullptr;   // n: sum over neighbours of (label+1); null when unlabelled
+  int32_t *heavy = nullptr;  // vertices with degree > kHeavyDegree
+  int64_t nheavy = 0;
+  // host statistics for the planner
+  std::vector<int64_t> label_count;  // vertices per label
+  std::vector<int64_t> deg_ge;       // deg_ge[d] = #vertices with degree >= d (d <= max_degree+1)
+  std::mutex mu;                     // guards ws
+  gsm::Workspace *ws = nullptr;
+};
+
+struct gsm_query {
+  int32_t q = 0;
+  std::vector<int32_t> edges;  // 2*ne
+  int32_t label[gsm::kMaxQ] = {0};
+  uint32_t adj[gsm::kMaxQ] = {0};  // adjacency bitmask by query id
+};
+
+namespace gsm {
+
+constexpr int64_t kHeavyDegree = 2048;
+
+// ------------------------------------------------------------------- plan --
+
+struct Plan {
+  int32_t q = 0;
+  int32_t order[kMaxQ];      // query id at position i
+  int32_t pos[kMaxQ];        // position of query id u
+  int32_t parent[kMaxQ];     // position of the tree parent
+  uint32_t backmask[kMaxQ];  // positions j < i adjacent to position i
+  // per query id (filter inputs)
+  int64_t qdeg[kMaxQ];
+  uint64_t qne[kMaxQ];
+  int32_t qlab[kMaxQ];
+};
+
+Plan make_plan(const gsm_graph &g, const gsm_query &q);
+
+// Query description handed to kernels by value.
+struct QueryArgs {
+  int32_t q;
+  int32_t root_bit;       // query id whose candidates are sliced, -1 none
+  uint32_t root_mod, root_rem;
+  int32_t use_deg, use_ne;
+  int32_t qlab[kMaxQ];
+  uint32_t qdeg[kMaxQ];
+  uint64_t qne[kMaxQ];
+};
+
+// One expansion level: rows hold positions 0..i-1; position i is matched.
+struct LevelArgs {
+  int32_t i;               // matched positions per input row
+  int32_t q;
+  uint32_t nbr_mask;       // positions j < i adjacent to position i
+  uint32_t qbit;           // cmask bit (query id) of position i
+  uint32_t next_nbr_mask;  // positions j <= i adjacent to position i+1 (0 at the last level)
+  int32_t out_col[kMaxQ];  // emit: output column (query id) of position j
+};
+
+// --------------------------------------------------------------- kernels --
+
+struct DeviceGraph {
+  const int64_t *rp;
+  const int32_t *col;
+  const int32_t *lab;
+  const uint32_t *deg;
+  const uint64_t *ne0;
+  int64_t n;
+};
+
+// Each launcher enqueues on `s` and returns immediately.
+void launch_graph_stats(const gsm_graph &g, hipStream_t s);
+void launch_filter_init(const DeviceGraph &g, const QueryArgs &qa, uint16_t *cmask, hipStream_t s);
+void launch_filter_refine(const DeviceGraph &g, const int32_t *heavy, int64_t nheavy,
+                          const QueryArgs &qa, const uint16_t *prev, uint16_t *next, hipStream_t s);
+// F1: vertices with bit `qbit` set (and degree >= 1 when need_edge); writes rows, W, counter.
+void launch_compact_first(const DeviceGraph &g, const uint16_t *cmask, uint32_t qbit, int need_edge,
+                          int32_t *rows, uint32_t *W, uint8_t *apos, uint64_t *counter,
+                          int32_t *emit_rows, uint64_t emit_cap, int32_t out_col0,
+                          hipStream_t s);
+// S[0..N] = exclusive scan of W[0..N-1]; N read from device *n_dev; scratch >= scan_scratch_bytes()
+size_t scan_scratch_elems();
+void launch_scan(const uint32_t *W, const uint64_t *n_dev, uint64_t *S, uint64_t *total_out,
+                 uint64_t *scratch, hipStream_t s);
+
+enum ExpandMode { kModeNext = 0, kModeCount = 1, kModeEmit = 2 };
+
+struct ExpandArgs {
+  DeviceGraph g;
+  const uint16_t *cmask;
+  const int32_t *rows_in;  // N x i
+  const uint8_t *apos_in;  // N
+  const uint64_t *S;       // N+1
+  uint64_t n_rows;         // N
+  uint64_t pair_begin, pair_end;
+  // kModeNext outputs
+  int32_t *rows_out;  // x (i+1)
+  uint32_t *W_out;
+  uint8_t *apos_out;
+  // shared counter: rows written (next) / embeddings counted (count, emit)
+  uint64_t *counter;
+  uint64_t *probes;  // binary-search steps of the back-edge checks
+  // kModeEmit output
+  int32_t *emit_rows;  // x q, query-id columns
+  uint64_t emit_base;  // rows already emitted before this launch (for the cap)
+  uint64_t emit_cap;
+  LevelArgs L;
+};
+
+void launch_expand(const ExpandArgs &a, int mode, int wg, int items, hipStream_t s);
+
+// -------------------------------------------------------------- workspace --
+
+struct Workspace {
+  DevBuf cmask, cmask2;
+  DevBuf rows[kMaxQ], W[kMaxQ], apos[kMaxQ], S[kMaxQ];
+  DevBuf counters;  // kMaxQ + 8 uint64
+  DevBuf scan_scratch;
+  DevBuf emit;      // staging for host-bound rows
+  uint64_t *h_counters = nullptr;  // pinned host mirror
+  std::vector<hipEvent_t> events;  // profiling event pool
+  Workspace();
+  ~Workspace();
+};
+
+}  // namespace gsm

@@ -1,0 +1,556 @@
+// HIP kernels of the matcher, written for gfx950 (wave64, 256 CUs in 8 XCDs).
+//
+// Everything here is integer work that streams or gathers CSR data from HBM;
+// nothing is a dense contraction, so no kernel uses the matrix cores.
+#include <hip/hip_runtime.h>
+
+#include "gsm_internal.h"
+
+namespace gsm {
+
+namespace {
+
+constexpr int kWave = 64;
+
+// Root-slice hash: the output of one splitmix64 step (Steele, Lea, Flood,
+// OOPSLA 2014) from state x, i.e. the finaliser applied to x + golden gamma.
+__device__ __forceinline__ uint64_t slice_mix(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
+  // number of set bits of mask below this lane
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+// Inclusive scan of a 64-bit value across the wave.
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint64_t o = __shfl_up(v, d, kWave);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread across the workgroup.  `sw` holds
+// one slot per wave.  Returns the prefix; *total gets the workgroup sum.
+template <int WG>
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *sw, uint64_t *total) {
+  constexpr int NW = WG / kWave;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  uint64_t inc = wave_incl_scan(v);
+  if (lane == kWave - 1) sw[wid] = inc;
+  __syncthreads();
+  uint64_t before = 0, sum = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    uint64_t x = sw[w];
+    if (w < wid) before += x;
+    sum += x;
+  }
+  __syncthreads();
+  *total = sum;
+  return before + inc - v;
+}
+
+__device__ __forceinline__ bool has_edge(const DeviceGraph &g, int32_t x, int32_t w,
+                                         uint32_t &probes) {
+  int64_t lo = g.rp[x];
+  const int64_t end = g.rp[x + 1];
+  int64_t hi = end;
+  while (lo < hi) {
+    ++probes;
+    int64_t mid = (lo + hi) >> 1;
+    if (g.col[mid] < w)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < end && g.col[lo] == w;
+}
+
+// ------------------------------------------------------------ graph stats --
+
+// deg[v] and NE0[v] = sum over neighbours of (label+1); 16 lanes per vertex.
+__global__ void k_graph_stats(const int64_t *rp, const int32_t *col, const int32_t *lab,
+                              int64_t n, uint32_t *deg, uint64_t *ne0) {
+  constexpr int G = 16;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sub = threadIdx.x & (G - 1);
+  for (int64_t v = gid / G; v < n; v += nthreads / G) {
+    const int64_t b = rp[v], e = rp[v + 1];
+    uint64_t s = 0;
+    if (lab)
+      for (int64_t k = b + sub; k < e; k += G) s += (uint64_t)lab[col[k]] + 1;
+#pragma unroll
+    for (int d = G / 2; d > 0; d >>= 1) s += __shfl_xor(s, d, G);
+    if (sub == 0) {
+      deg[v] = (uint32_t)(e - b);
+      if (ne0) ne0[v] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- filter --
+
+__device__ __forceinline__ uint16_t candidate_bits(const QueryArgs &qa, int32_t lv, uint32_t d,
+                                                   uint64_t ne, uint64_t v) {
+  uint32_t m = 0;
+  for (int u = 0; u < qa.q; ++u) {
+    bool ok = (lv == qa.qlab[u]);
+    ok = ok && (!qa.use_deg || d >= qa.qdeg[u]);
+    ok = ok && (!qa.use_ne || ne >= qa.qne[u]);
+    if (u == qa.root_bit) ok = ok && (slice_mix(v) % qa.root_mod == qa.root_rem);
+    m |= (uint32_t)ok << u;
+  }
+  return (uint16_t)m;
+}
+
+__global__ void k_filter_init(DeviceGraph g, QueryArgs qa, uint16_t *cmask) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
+    const int32_t lv = g.lab ? g.lab[v] : 0;
+    const uint32_t d = g.deg[v];
+    const uint64_t ne = g.ne0 ? g.ne0[v] : (uint64_t)d;
+    cmask[v] = candidate_bits(qa, lv, d, ne, (uint64_t)v);
+  }
+}
+
+__device__ __forceinline__ uint16_t refine_bits(const QueryArgs &qa, uint16_t pm, uint32_t c,
+                                                uint64_t s) {
+  uint32_t m = 0;
+  for (int u = 0; u < qa.q; ++u) {
+    bool ok = (pm >> u) & 1;
+    ok = ok && (!qa.use_deg || c >= qa.qdeg[u]);
+    ok = ok && (!qa.use_ne || s >= qa.qne[u]);
+    m |= (uint32_t)ok << u;
+  }
+  return (uint16_t)m;
+}
+
+// One refinement round for vertices of degree <= kHeavyDegree; 16 lanes per vertex.
+__global__ void k_refine_light(DeviceGraph g, QueryArgs qa, const uint16_t *prev, uint16_t *next) {
+  constexpr int G = 16;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sub = threadIdx.x & (G - 1);
+  for (int64_t v = gid / G; v < g.n; v += nthreads / G) {
+    const uint16_t pm = prev[v];
+    const int64_t b = g.rp[v], e = g.rp[v + 1];
+    if (e - b > kHeavyDegree) continue;  // k_refine_heavy writes it
+    if (pm == 0) {
+      if (sub == 0) next[v] = 0;
+      continue;
+    }
+    uint32_t c = 0;
+    uint64_t s = 0;
+    for (int64_t k = b + sub; k < e; k += G) {
+      const int32_t w = g.col[k];
+      if (prev[w]) {
+        c += 1;
+        s += g.lab ? (uint64_t)g.lab[w] + 1 : 1;
+      }
+    }
+#pragma unroll
+    for (int d = G / 2; d > 0; d >>= 1) {
+      c += __shfl_xor(c, d, G);
+      s += __shfl_xor(s, d, G);
+    }
+    if (sub == 0) next[v] = refine_bits(qa, pm, c, s);
+  }
+}
+
+// One refinement round for the high-degree vertices; one workgroup per vertex.
+__global__ __launch_bounds__(256) void k_refine_heavy(DeviceGraph g, QueryArgs qa,
+                                                      const int32_t *heavy, int64_t nheavy,
+                                                      const uint16_t *prev, uint16_t *next) {
+  __shared__ uint64_t sw[256 / kWave];
+  for (int64_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
+    const int32_t v = heavy[h];
+    const uint16_t pm = prev[v];
+    if (pm == 0) {  // uniform across the workgroup
+      if (threadIdx.x == 0) next[v] = 0;
+      continue;
+    }
+    const int64_t b = g.rp[v], e = g.rp[v + 1];
+    uint64_t c = 0, s = 0;
+    for (int64_t k = b + threadIdx.x; k < e; k += blockDim.x) {
+      const int32_t w = g.col[k];
+      if (prev[w]) {
+        c += 1;
+        s += g.lab ? (uint64_t)g.lab[w] + 1 : 1;
+      }
+    }
+    uint64_t tc, ts;
+    block_excl_scan<256>(c, sw, &tc);
+    block_excl_scan<256>(s, sw, &ts);
+    if (threadIdx.x == 0) next[v] = refine_bits(qa, pm, (uint32_t)tc, ts);
+  }
+}
+
+// ------------------------------------------------------ first frontier --
+
+__global__ __launch_bounds__(256) void k_compact_first(DeviceGraph g, const uint16_t *cmask,
+                                                       uint32_t qbit, int need_edge, int32_t *rows,
+                                                       uint32_t *W, uint8_t *apos,
+                                                       uint64_t *counter, int32_t *emit_rows,
+                                                       uint64_t emit_cap, int32_t out_col0) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // every lane of the wave runs the same number of iterations
+  const int64_t base0 = start - (threadIdx.x & (kWave - 1));
+  for (int64_t vb = base0; vb < g.n; vb += stride) {
+    const int64_t v = vb + (threadIdx.x & (kWave - 1));
+    bool keep = false;
+    uint32_t d = 0;
+    if (v < g.n) {
+      d = g.deg[v];
+      keep = ((cmask[v] >> qbit) & 1) && (!need_edge || d > 0);
+    }
+    const uint64_t mask = wave_ballot(keep);
+    if (mask == 0) continue;
+    uint64_t base = 0;
+    if ((threadIdx.x & (kWave - 1)) == 0) base = atomicAdd((unsigned long long *)counter, (unsigned long long)__popcll(mask));
+    base = __shfl(base, 0, kWave);
+    if (keep) {
+      const uint64_t pos = base + lane_prefix(mask);
+      if (rows) {
+        rows[pos] = (int32_t)v;
+        W[pos] = d;
+        apos[pos] = 0;
+      }
+      if (emit_rows && pos < emit_cap) emit_rows[pos] = (int32_t)v;
+      (void)out_col0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ scan --
+
+constexpr int kScanBlocks = 512;
+constexpr int kScanWG = 256;
+constexpr int kScanItems = 4;
+
+__global__ __launch_bounds__(kScanWG) void k_scan_reduce(const uint32_t *W, const uint64_t *n_dev,
+                                                         uint64_t *partial) {
+  __shared__ uint64_t sw[kScanWG / kWave];
+  const uint64_t N = *n_dev;
+  const uint64_t per = (N + kScanBlocks - 1) / kScanBlocks;
+  const uint64_t b = (uint64_t)blockIdx.x * per, e = min(N, b + per);
+  uint64_t s = 0;
+  for (uint64_t k = b + threadIdx.x; k < e; k += kScanWG) s += W[k];
+  uint64_t tot;
+  block_excl_scan<kScanWG>(s, sw, &tot);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanWG) void k_scan_partials(uint64_t *partial, const uint64_t *n_dev,
+                                                           uint64_t *S, uint64_t *total_out) {
+  __shared__ uint64_t sw[kScanWG / kWave];
+  constexpr int per = kScanBlocks / kScanWG;
+  uint64_t v[per];
+  uint64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < per; ++j) {
+    v[j] = partial[threadIdx.x * per + j];
+    s += v[j];
+  }
+  uint64_t tot;
+  uint64_t run = block_excl_scan<kScanWG>(s, sw, &tot);
+#pragma unroll
+  for (int j = 0; j < per; ++j) {
+    partial[threadIdx.x * per + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 0) {
+    S[*n_dev] = tot;
+    if (total_out) *total_out = tot;
+  }
+}
+
+__global__ __launch_bounds__(kScanWG) void k_scan_down(const uint32_t *W, const uint64_t *n_dev,
+                                                       const uint64_t *partial, uint64_t *S) {
+  __shared__ uint64_t sw[kScanWG / kWave];
+  const uint64_t N = *n_dev;
+  const uint64_t per = (N + kScanBlocks - 1) / kScanBlocks;
+  const uint64_t b = (uint64_t)blockIdx.x * per, e = min(N, b + per);
+  uint64_t carry = partial[blockIdx.x];
+  constexpr int T = kScanWG * kScanItems;
+  for (uint64_t t0 = b; t0 < e; t0 += T) {
+    uint64_t v[kScanItems];
+    uint64_t s = 0;
+    const uint64_t k0 = t0 + (uint64_t)threadIdx.x * kScanItems;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      v[j] = (k0 + j < e) ? W[k0 + j] : 0;
+      s += v[j];
+    }
+    uint64_t tot;
+    uint64_t run = carry + block_excl_scan<kScanWG>(s, sw, &tot);
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      if (k0 + j < e) S[k0 + j] = run;
+      run += v[j];
+    }
+    carry += tot;
+  }
+}
+
+// --------------------------------------------------------------- expand --
+//
+// One launch expands rows of level i over a range of the flat pair space.
+// Pair t belongs to row r with S[r] <= t < S[r+1]; its candidate is the
+// (t - S[r])-th neighbour of the row's anchor (the earlier-matched neighbour
+// of the new query vertex with the smallest data degree, chosen when the row
+// was written).  Lanes of a wave take consecutive pairs, so neighbour reads
+// of one row are coalesced.  Survivors of the candidate-set test,
+// injectivity and every back-edge are compacted with a wave ballot, a
+// workgroup scan and one atomic per tile.
+template <int WG, int ITEMS, int MODE>
+__global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
+  constexpr int TILE = WG * ITEMS;
+  __shared__ uint64_t sS[TILE + 1];
+  __shared__ uint64_t sw[WG / kWave];
+  __shared__ uint64_t s_r0, s_base;
+
+  const int tid = threadIdx.x;
+  const int i = a.L.i;
+  const uint64_t npairs = a.pair_end - a.pair_begin;
+  const uint64_t ntiles = (npairs + TILE - 1) / TILE;
+  const uint32_t G = gridDim.x, b = blockIdx.x;
+  // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
+  // contiguous run of tiles so neighbouring tiles share its L2.
+  const uint64_t lb = (G % 8 == 0) ? (uint64_t)(b % 8) * (G / 8) + b / 8 : b;
+  const uint32_t inj_mask = ((1u << i) - 1u) & ~a.L.nbr_mask;
+  uint64_t wg_count = 0;
+  uint32_t probes = 0;
+
+  for (uint64_t tile = lb; tile < ntiles; tile += G) {
+    const uint64_t t0 = a.pair_begin + tile * TILE;
+    const uint64_t t1 = min(t0 + (uint64_t)TILE, a.pair_end);
+    if (tid == 0) {
+      uint64_t lo = 0, hi = a.n_rows;  // S[lo] <= t0 < S[hi]
+      while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (a.S[mid] <= t0)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      s_r0 = lo;
+    }
+    __syncthreads();
+    const uint64_t r0 = s_r0;
+    for (int k = tid; k <= TILE; k += WG) {
+      const uint64_t r = r0 + k;
+      sS[k] = (r <= a.n_rows) ? a.S[r] : ~0ull;
+    }
+    __syncthreads();
+
+    uint32_t keepbits = 0;
+    int32_t wv[ITEMS];
+    uint32_t rk[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      wv[it] = 0;
+      rk[it] = 0;
+      const uint64_t t = t0 + (uint64_t)it * WG + tid;
+      if (t >= t1) continue;
+      int lo = 0, hi = TILE;  // sS[lo] <= t < sS[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sS[mid] <= t)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      const uint64_t r = r0 + lo;
+      const int32_t *row = a.rows_in + r * (uint64_t)i;
+      const int ap = a.apos_in[r];
+      const int32_t anc = row[ap];
+      const int32_t w = a.g.col[a.g.rp[anc] + (int64_t)(t - sS[lo])];
+      bool keep = (a.cmask[w] >> a.L.qbit) & 1;
+      uint32_t m = inj_mask;
+      while (keep && m) {
+        const int j = __builtin_ctz(m);
+        m &= m - 1;
+        keep = row[j] != w;
+      }
+      m = a.L.nbr_mask & ~(1u << ap);
+      while (keep && m) {
+        const int j = __builtin_ctz(m);
+        m &= m - 1;
+        keep = has_edge(a.g, row[j], w, probes);
+      }
+      if (keep) {
+        keepbits |= 1u << it;
+        wv[it] = w;
+        rk[it] = (uint32_t)lo;
+      }
+    }
+
+    const uint32_t c = __builtin_popcount(keepbits);
+    if (MODE == kModeCount) {
+      wg_count += c;
+      continue;
+    }
+    uint64_t total;
+    const uint64_t off = block_excl_scan<WG>(c, sw, &total);
+    if (tid == 0) s_base = total ? atomicAdd((unsigned long long *)a.counter, (unsigned long long)total) : 0;
+    __syncthreads();
+    uint64_t pos = s_base + off;
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      if (!((keepbits >> it) & 1)) continue;
+      const uint64_t r = r0 + rk[it];
+      const int32_t *row = a.rows_in + r * (uint64_t)i;
+      const int32_t w = wv[it];
+      if (MODE == kModeNext) {
+        int32_t *o = a.rows_out + pos * (uint64_t)(i + 1);
+        for (int j = 0; j < i; ++j) o[j] = row[j];
+        o[i] = w;
+        // anchor of the next position: earlier neighbour with the smallest degree
+        uint32_t m = a.L.next_nbr_mask, best = 0xffffffffu;
+        int bj = 0;
+        while (m) {
+          const int j = __builtin_ctz(m);
+          m &= m - 1;
+          const uint32_t d = a.g.deg[j == i ? w : row[j]];
+          if (d < best) {
+            best = d;
+            bj = j;
+          }
+        }
+        a.W_out[pos] = best;
+        a.apos_out[pos] = (uint8_t)bj;
+      } else {  // kModeEmit
+        const uint64_t slot = pos - a.emit_base;
+        if (slot < a.emit_cap) {
+          int32_t *o = a.emit_rows + slot * (uint64_t)a.L.q;
+          for (int j = 0; j < i; ++j) o[a.L.out_col[j]] = row[j];
+          o[a.L.out_col[i]] = w;
+        }
+      }
+      ++pos;
+    }
+  }
+  if (MODE == kModeCount) {
+    uint64_t total;
+    block_excl_scan<WG>(wg_count, sw, &total);
+    if (tid == 0 && total) atomicAdd((unsigned long long *)a.counter, (unsigned long long)total);
+  }
+  if (a.probes) {
+    uint64_t total;
+    block_excl_scan<WG>(probes, sw, &total);
+    if (tid == 0 && total) atomicAdd((unsigned long long *)a.probes, (unsigned long long)total);
+  }
+}
+
+template <int WG, int ITEMS>
+void launch_expand_t(const ExpandArgs &a, int mode, hipStream_t s) {
+  constexpr uint64_t TILE = (uint64_t)WG * ITEMS;
+  const uint64_t ntiles = (a.pair_end - a.pair_begin + TILE - 1) / TILE;
+  if (ntiles == 0) return;
+  uint64_t grid = ntiles;
+  const uint64_t kMaxGrid = 1u << 20;
+  if (grid > kMaxGrid) grid = kMaxGrid;
+  if (grid >= 8) grid &= ~7ull;
+  switch (mode) {
+    case kModeNext:
+      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeNext>), dim3((uint32_t)grid), dim3(WG), 0, s, a);
+      break;
+    case kModeCount:
+      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeCount>), dim3((uint32_t)grid), dim3(WG), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeEmit>), dim3((uint32_t)grid), dim3(WG), 0, s, a);
+      break;
+  }
+}
+
+template <int WG>
+void launch_expand_wg(const ExpandArgs &a, int mode, int items, hipStream_t s) {
+  switch (items) {
+    case 1: launch_expand_t<WG, 1>(a, mode, s); break;
+    case 2: launch_expand_t<WG, 2>(a, mode, s); break;
+    case 8: launch_expand_t<WG, 8>(a, mode, s); break;
+    default: launch_expand_t<WG, 4>(a, mode, s); break;
+  }
+}
+
+uint32_t grid_for(int64_t work, int wg, uint32_t cap) {
+  int64_t g = (work + wg - 1) / wg;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (uint32_t)g;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- launchers --
+
+void launch_graph_stats(const gsm_graph &g, hipStream_t s) {
+  if (g.n == 0) return;
+  hipLaunchKernelGGL(k_graph_stats, dim3(grid_for(g.n * 16, 256, 1u << 16)), dim3(256), 0, s,
+                     g.rp, g.col, g.lab, g.n, g.deg, g.ne0);
+  GSM_HIP(hipGetLastError());
+}
+
+void launch_filter_init(const DeviceGraph &g, const QueryArgs &qa, uint16_t *cmask, hipStream_t s) {
+  if (g.n == 0) return;
+  hipLaunchKernelGGL(k_filter_init, dim3(grid_for(g.n, 256, 1u << 16)), dim3(256), 0, s, g, qa, cmask);
+  GSM_HIP(hipGetLastError());
+}
+
+void launch_filter_refine(const DeviceGraph &g, const int32_t *heavy, int64_t nheavy,
+                          const QueryArgs &qa, const uint16_t *prev, uint16_t *next, hipStream_t s) {
+  if (g.n == 0) return;
+  hipLaunchKernelGGL(k_refine_light, dim3(grid_for(g.n * 16, 256, 1u << 16)), dim3(256), 0, s, g, qa,
+                     prev, next);
+  GSM_HIP(hipGetLastError());
+  if (nheavy > 0) {
+    hipLaunchKernelGGL(k_refine_heavy, dim3(grid_for(nheavy * 256, 256, 1u << 16)), dim3(256), 0, s, g,
+                       qa, heavy, nheavy, prev, next);
+    GSM_HIP(hipGetLastError());
+  }
+}
+
+void launch_compact_first(const DeviceGraph &g, const uint16_t *cmask, uint32_t qbit, int need_edge,
+                          int32_t *rows, uint32_t *W, uint8_t *apos, uint64_t *counter,
+                          int32_t *emit_rows, uint64_t emit_cap, int32_t out_col0, hipStream_t s) {
+  if (g.n == 0) return;
+  hipLaunchKernelGGL(k_compact_first, dim3(grid_for(g.n, 256, 1u << 14)), dim3(256), 0, s, g, cmask,
+                     qbit, need_edge, rows, W, apos, counter, emit_rows, emit_cap, out_col0);
+  GSM_HIP(hipGetLastError());
+}
+
+size_t scan_scratch_elems() { return kScanBlocks; }
+
+void launch_scan(const uint32_t *W, const uint64_t *n_dev, uint64_t *S, uint64_t *total_out,
+                 uint64_t *scratch, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(kScanWG), 0, s, W, n_dev, scratch);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanWG), 0, s, scratch, n_dev, S, total_out);
+  hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kScanWG), 0, s, W, n_dev, scratch, S);
+  GSM_HIP(hipGetLastError());
+}
+
+void launch_expand(const ExpandArgs &a, int mode, int wg, int items, hipStream_t s) {
+  if (a.pair_end <= a.pair_begin) return;
+  switch (wg) {
+    case 128: launch_expand_wg<128>(a, mode, items, s); break;
+    case 512: launch_expand_wg<512>(a, mode, items, s); break;
+    default: launch_expand_wg<256>(a, mode, items, s); break;
+  }
+  GSM_HIP(hipGetLastError());
+}
+
+}  // namespace gsm

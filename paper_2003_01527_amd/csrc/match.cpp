@@ -1,0 +1,476 @@
+// Single-query driver: filter, first frontier, then level-by-level expansion
+// cut into memory-bounded chunks (depth-first over chunks, breadth-first
+// inside a chunk), as in the verification loop of the paper's Alg. 1.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+#include "gsm_internal.h"
+
+namespace gsm {
+
+namespace {
+
+// counters[] slots in the workspace
+constexpr int kCntRows = 0;     // [1..15]: rows written at level i
+constexpr int kCntPairs = 16;   // [16+i]: scan total of level i
+constexpr int kCntResult = 32;  // embeddings counted at the last level
+constexpr int kCntProbes = 33;  // binary-search steps
+
+struct Options {
+  uint64_t budget = uint64_t(4) << 30;
+  int rounds = 1, use_deg = 1, use_ne = 1;
+  bool rows_dev = false;
+  hipStream_t stream = nullptr;
+  int root_q = -1;
+  uint32_t root_mod = 0, root_rem = 0;
+  gsm_emit_fn emit = nullptr;
+  void *emit_ctx = nullptr;
+  gsm_stats *stats = nullptr;
+  int items = 4, wg = 256;
+  bool profile = false;
+};
+
+Options read_opts(const gsm_match_opts *o, int q) {
+  Options r;
+  if (!o) return r;
+  if (o->struct_size < sizeof(uint32_t)) throw Error{GSM_E_INVALID_ARG, "opts.struct_size not set"};
+  if (o->memory_budget_bytes) r.budget = o->memory_budget_bytes;
+  r.rounds = o->filter_rounds;
+  r.use_deg = o->use_degree;
+  r.use_ne = o->use_ne;
+  r.rows_dev = o->rows_on_device != 0;
+  r.stream = (hipStream_t)o->hip_stream;
+  r.root_q = o->root_qvertex;
+  r.root_mod = o->root_mod;
+  r.root_rem = o->root_rem;
+  r.emit = o->emit;
+  r.emit_ctx = o->emit_ctx;
+  r.stats = o->stats;
+  if (o->tile_items) r.items = o->tile_items;
+  if (o->wg_size) r.wg = o->wg_size;
+  r.profile = o->profile != 0;
+  if (r.rounds < 0 || r.rounds > 64) throw Error{GSM_E_INVALID_ARG, "filter_rounds out of [0, 64]"};
+  if (r.root_q >= q) throw Error{GSM_E_INVALID_ARG, "root_qvertex >= q"};
+  if (r.root_q >= 0 && r.root_mod == 0) throw Error{GSM_E_INVALID_ARG, "root_mod must be > 0"};
+  if (r.root_q >= 0 && r.root_rem >= r.root_mod) throw Error{GSM_E_INVALID_ARG, "root_rem >= root_mod"};
+  if (r.items != 1 && r.items != 2 && r.items != 4 && r.items != 8)
+    throw Error{GSM_E_INVALID_ARG, "tile_items must be 1, 2, 4 or 8"};
+  if (r.wg != 128 && r.wg != 256 && r.wg != 512)
+    throw Error{GSM_E_INVALID_ARG, "wg_size must be 128, 256 or 512"};
+  return r;
+}
+
+struct Matcher {
+  gsm_graph &g;
+  const gsm_query &qh;
+  Plan p;
+  Options o;
+  Workspace &ws;
+  hipStream_t s;
+  DeviceGraph dg;
+  uint64_t cap[kMaxQ];  // max rows per level buffer
+  uint64_t *dcnt;       // device counters
+  // output
+  int32_t *rows_user = nullptr;
+  uint64_t rows_cap = 0;
+  bool emit_host = false;  // rows pass through the staging buffer to the host
+  uint64_t staged_cap = 0;
+  uint64_t host_rows_done = 0;
+  bool cancelled = false;
+  std::vector<int32_t> host_stage;
+  gsm_stats st;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;
+  size_t ev_next = 0;
+
+  Matcher(gsm_graph &g_, const gsm_query &q_, const Options &o_, Workspace &ws_)
+      : g(g_), qh(q_), o(o_), ws(ws_), s(o_.stream) {
+    p = make_plan(g, qh);
+    dg = DeviceGraph{g.rp, g.col, g.lab, g.deg, g.ne0, g.n};
+    dcnt = ws.counters.as<uint64_t>();
+    std::memset(&st, 0, sizeof(st));
+    st.struct_size = sizeof(st);
+    st.q = p.q;
+  }
+
+  QueryArgs query_args() const {
+    QueryArgs qa;
+    std::memset(&qa, 0, sizeof(qa));
+    qa.q = p.q;
+    qa.root_bit = o.root_q;
+    qa.root_mod = o.root_mod ? o.root_mod : 1;
+    qa.root_rem = o.root_rem;
+    qa.use_deg = o.use_deg;
+    qa.use_ne = o.use_ne;
+    for (int u = 0; u < p.q; ++u) {
+      qa.qlab[u] = p.qlab[u];
+      qa.qdeg[u] = (uint32_t)p.qdeg[u];
+      qa.qne[u] = p.qne[u];
+    }
+    return qa;
+  }
+
+  // Filter into ws.cmask (query-id bits).
+  void filter() {
+    ws.cmask.reserve(std::max<int64_t>(g.n, 1) * sizeof(uint16_t));
+    const QueryArgs qa = query_args();
+    launch_filter_init(dg, qa, ws.cmask.as<uint16_t>(), s);
+    st.filter_bytes += (uint64_t)g.n * (4 + 4 + (g.ne0 ? 8 : 0) + 2);
+    if (o.rounds > 0) ws.cmask2.reserve(std::max<int64_t>(g.n, 1) * sizeof(uint16_t));
+    for (int r = 0; r < o.rounds; ++r) {
+      launch_filter_refine(dg, g.heavy, g.nheavy, qa, ws.cmask.as<uint16_t>(),
+                           ws.cmask2.as<uint16_t>(), s);
+      std::swap(ws.cmask.ptr, ws.cmask2.ptr);
+      std::swap(ws.cmask.bytes, ws.cmask2.bytes);
+      st.filter_bytes += (uint64_t)(g.n + 1) * 8 + (uint64_t)g.nnz * (4 + 2 + (g.lab ? 4 : 0)) +
+                         (uint64_t)g.n * 4;
+    }
+  }
+
+  void sync() { GSM_HIP(hipStreamSynchronize(s)); }
+
+  void fetch_counters() {
+    GSM_HIP(hipMemcpyAsync(ws.h_counters, dcnt, 64 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    sync();
+  }
+
+  void zero_counter(int slot) {
+    GSM_HIP(hipMemsetAsync(dcnt + slot, 0, sizeof(uint64_t), s));
+  }
+
+  std::pair<hipEvent_t, hipEvent_t> next_events() {
+    while (ws.events.size() < 2 * (ev_next + 1)) {
+      hipEvent_t e;
+      GSM_HIP(hipEventCreate(&e));
+      ws.events.push_back(e);
+    }
+    auto pr = std::make_pair(ws.events[2 * ev_next], ws.events[2 * ev_next + 1]);
+    ++ev_next;
+    return pr;
+  }
+
+  void expand(ExpandArgs &a, int mode) {
+    a.probes = dcnt + kCntProbes;
+    if (o.profile) {
+      auto pr = next_events();
+      GSM_HIP(hipEventRecord(pr.first, s));
+      launch_expand(a, mode, o.wg, o.items, s);
+      GSM_HIP(hipEventRecord(pr.second, s));
+      ev_pairs.push_back(pr);
+    } else {
+      launch_expand(a, mode, o.wg, o.items, s);
+    }
+    st.expand_launches++;
+  }
+
+  // Level capacities from the budget.  Fixed: two cmask arrays, the first
+  // frontier (<= n rows), counters.  The rest is split evenly over levels
+  // 2..q-1 plus the host staging buffer when rows go to the host.
+  void plan_capacity() {
+    const uint64_t n = (uint64_t)std::max<int64_t>(g.n, 1);
+    const uint64_t fixed = 2 * n * 2 + n * (4 + 4 + 1) + (n + 1) * 8 + 4096;
+    if (o.budget < fixed + 64) throw Error{GSM_E_BUDGET, "memory budget below the first frontier"};
+    const uint64_t rest = o.budget - fixed;
+    const int shares = std::max(0, p.q - 2) + (emit_host ? 1 : 0);
+    for (int i = 0; i < kMaxQ; ++i) cap[i] = 0;
+    cap[1] = n;
+    for (int i = 2; i < p.q; ++i) {
+      cap[i] = rest / shares / (uint64_t)(4 * i + 13);
+      if (cap[i] < 1) throw Error{GSM_E_BUDGET, "memory budget below one row of level " + std::to_string(i)};
+    }
+    if (emit_host) {
+      staged_cap = std::min<uint64_t>(rest / shares / (uint64_t)(4 * p.q), uint64_t(1) << 26);
+      if (staged_cap < 1) throw Error{GSM_E_BUDGET, "memory budget below one output row"};
+    }
+    // give back buffers larger than this call's share
+    for (int i = 2; i < kMaxQ; ++i) {
+      if (ws.rows[i].bytes > std::max<uint64_t>(cap[i], 1) * 4 * i + 256) ws.rows[i].release();
+      if (ws.S[i].bytes > (std::max<uint64_t>(cap[i], 1) + 1) * 8 + 256) ws.S[i].release();
+      if (ws.W[i].bytes > std::max<uint64_t>(cap[i], 1) * 4 + 256) ws.W[i].release();
+      if (ws.apos[i].bytes > std::max<uint64_t>(cap[i], 1) + 256) ws.apos[i].release();
+    }
+  }
+
+  void reserve_level(int i, uint64_t rows) {
+    ws.rows[i].reserve(rows * 4 * (uint64_t)i);
+    ws.W[i].reserve(rows * 4);
+    ws.apos[i].reserve(rows);
+    ws.S[i].reserve((rows + 1) * 8);
+  }
+
+  LevelArgs level_args(int i) const {
+    LevelArgs L;
+    std::memset(&L, 0, sizeof(L));
+    L.i = i;
+    L.q = p.q;
+    L.nbr_mask = p.backmask[i];
+    L.qbit = (uint32_t)p.order[i];
+    L.next_nbr_mask = (i + 1 < p.q) ? p.backmask[i + 1] : 0;
+    for (int j = 0; j < p.q; ++j) L.out_col[j] = p.order[j];
+    return L;
+  }
+
+  // Hands staged rows [0, nrows) to the sink.
+  void drain_stage(uint64_t nrows) {
+    if (nrows == 0) return;
+    if (o.emit && o.rows_dev) {  // device sink: the callback reads device memory
+      sync();
+      if (o.emit(o.emit_ctx, ws.emit.as<int32_t>(), nrows, p.q) != 0) cancelled = true;
+    } else if (o.emit) {
+      host_stage.resize(nrows * (uint64_t)p.q);
+      GSM_HIP(hipMemcpyAsync(host_stage.data(), ws.emit.ptr, nrows * p.q * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+      sync();
+      if (o.emit(o.emit_ctx, host_stage.data(), nrows, p.q) != 0) cancelled = true;
+    } else if (rows_user && host_rows_done < rows_cap) {
+      const uint64_t take = std::min(nrows, rows_cap - host_rows_done);
+      GSM_HIP(hipMemcpyAsync(rows_user + host_rows_done * p.q, ws.emit.ptr, take * p.q * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+      sync();
+    }
+    host_rows_done += nrows;
+  }
+
+  // rows of level i (i matched vertices) are in ws.*[i], their count in dcnt[i]
+  void process_level(int i) {
+    launch_scan(ws.W[i].as<uint32_t>(), dcnt + kCntRows + i, ws.S[i].as<uint64_t>(),
+                dcnt + kCntPairs + i, ws.scan_scratch.as<uint64_t>(), s);
+    fetch_counters();
+    const uint64_t N = ws.h_counters[kCntRows + i];
+    const uint64_t P = ws.h_counters[kCntPairs + i];
+    st.rows[i - 1] += N;
+    st.pairs[i] += P;
+    if (P == 0) return;
+    const bool last = (i == p.q - 1);
+    ExpandArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = dg;
+    a.cmask = ws.cmask.as<uint16_t>();
+    a.rows_in = ws.rows[i].as<int32_t>();
+    a.apos_in = ws.apos[i].as<uint8_t>();
+    a.S = ws.S[i].as<uint64_t>();
+    a.n_rows = N;
+    a.L = level_args(i);
+    if (!last) {
+      const uint64_t c = cap[i + 1];
+      for (uint64_t b = 0; b < P && !cancelled; b += c) {
+        const uint64_t e = std::min(P, b + c);
+        reserve_level(i + 1, e - b);
+        zero_counter(kCntRows + i + 1);
+        a.pair_begin = b;
+        a.pair_end = e;
+        a.rows_out = ws.rows[i + 1].as<int32_t>();
+        a.W_out = ws.W[i + 1].as<uint32_t>();
+        a.apos_out = ws.apos[i + 1].as<uint8_t>();
+        a.counter = dcnt + kCntRows + i + 1;
+        expand(a, kModeNext);
+        st.chunks[i]++;
+        process_level(i + 1);
+      }
+      return;
+    }
+    a.counter = dcnt + kCntResult;
+    if (!rows_user && !o.emit) {  // count only
+      a.pair_begin = 0;
+      a.pair_end = P;
+      expand(a, kModeCount);
+      st.chunks[i]++;
+    } else if (!emit_host) {  // rows straight into the caller's device buffer
+      a.pair_begin = 0;
+      a.pair_end = P;
+      a.emit_rows = rows_user;
+      a.emit_base = 0;
+      a.emit_cap = rows_cap;
+      expand(a, kModeEmit);
+      st.chunks[i]++;
+    } else {  // through the staging buffer, one chunk at a time
+      ws.emit.reserve(std::min(staged_cap, P) * p.q * sizeof(int32_t));
+      for (uint64_t b = 0; b < P && !cancelled; b += staged_cap) {
+        const uint64_t e = std::min(P, b + staged_cap);
+        a.pair_begin = b;
+        a.pair_end = e;
+        a.emit_rows = ws.emit.as<int32_t>();
+        a.emit_base = host_rows_done;
+        a.emit_cap = staged_cap;
+        expand(a, kModeEmit);
+        st.chunks[i]++;
+        fetch_counters();
+        drain_stage(ws.h_counters[kCntResult] - host_rows_done);
+      }
+    }
+  }
+
+  uint64_t run() {
+    GSM_HIP(hipMemsetAsync(dcnt, 0, 64 * sizeof(uint64_t), s));
+    filter();
+    const int q = p.q;
+    const uint32_t qbit0 = (uint32_t)p.order[0];
+    if (q == 1) {
+      // the candidates of the single query vertex are the embeddings
+      int32_t *dst = nullptr;
+      uint64_t dcap = 0;
+      if (rows_user || o.emit) {
+        if (!emit_host) {
+          dst = rows_user;
+          dcap = rows_cap;
+        } else {
+          ws.emit.reserve(std::max<int64_t>(g.n, 1) * sizeof(int32_t));
+          dst = ws.emit.as<int32_t>();
+          dcap = (uint64_t)g.n;
+        }
+      }
+      launch_compact_first(dg, ws.cmask.as<uint16_t>(), qbit0, 0, nullptr, nullptr, nullptr,
+                           dcnt + kCntResult, dst, dcap, 0, s);
+      fetch_counters();
+      const uint64_t count = ws.h_counters[kCntResult];
+      st.rows[0] = count;
+      st.candidates_root = count;
+      if (emit_host) drain_stage(count);
+      return count;
+    }
+    reserve_level(1, (uint64_t)std::max<int64_t>(g.n, 1));
+    launch_compact_first(dg, ws.cmask.as<uint16_t>(), qbit0, 1, ws.rows[1].as<int32_t>(),
+                         ws.W[1].as<uint32_t>(), ws.apos[1].as<uint8_t>(), dcnt + kCntRows + 1,
+                         nullptr, 0, 0, s);
+    process_level(1);
+    fetch_counters();
+    st.candidates_root = st.rows[0];
+    st.probes = ws.h_counters[kCntProbes];
+    st.rows[q - 1] = ws.h_counters[kCntResult];
+    return ws.h_counters[kCntResult];
+  }
+
+  // Algorithmic bytes of the expansion launches (what the method must move):
+  // per input row its ids, anchor position, scan entry and two offsets; per
+  // pair a neighbour id and a candidate-mask entry; per binary-search step
+  // one neighbour id plus two offsets per checked back-edge list (counted as
+  // 4 bytes a step); per written row its ids, weight and anchor position.
+  void finish_stats(uint64_t count) {
+    uint64_t b = 0;
+    for (int i = 1; i < p.q; ++i) {
+      b += st.rows[i - 1] * (4ull * i + 1 + 8 + 16) + st.pairs[i] * (4 + 2);
+      if (i + 1 < p.q) b += st.rows[i] * (4ull * (i + 1) + 4 + 1);
+    }
+    b += st.probes * 4;
+    if (rows_user || o.emit) b += count * 4ull * p.q;
+    st.alg_bytes = b;
+    if (o.profile) {
+      double ms = 0;
+      for (auto &pr : ev_pairs) {
+        float t = 0;
+        GSM_HIP(hipEventElapsedTime(&t, pr.first, pr.second));
+        ms += t;
+      }
+      st.ms_expand = ms;
+    }
+  }
+};
+
+Workspace &acquire_ws(gsm_graph &g) {
+  if (!g.ws) g.ws = new Workspace();
+  return *g.ws;
+}
+
+}  // namespace
+
+}  // namespace gsm
+
+using gsm::Error;
+
+extern "C" {
+
+void gsm_match_opts_init(gsm_match_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(*o);
+  o->filter_rounds = 1;
+  o->use_degree = 1;
+  o->use_ne = 1;
+  o->root_qvertex = -1;
+}
+
+gsm_status gsm_filter(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, uint16_t *cmask) {
+  try {
+    if (!g || !qh || !cmask) {
+      gsm::set_error("gsm_filter: NULL argument");
+      return GSM_E_INVALID_ARG;
+    }
+    const gsm::Options o = gsm::read_opts(opts, qh->q);
+    std::lock_guard<std::mutex> lk(g->mu);
+    gsm::Workspace &ws = gsm::acquire_ws(*g);
+    gsm::Matcher m(*g, *qh, o, ws);
+    m.filter();
+    if (g->n)
+      GSM_HIP(hipMemcpyAsync(cmask, ws.cmask.ptr, g->n * sizeof(uint16_t), hipMemcpyDeviceToHost, m.s));
+    m.sync();
+    return GSM_OK;
+  } catch (const Error &e) {
+    gsm::set_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc &) {
+    gsm::set_error("host allocation failed");
+    return GSM_E_OOM;
+  }
+}
+
+gsm_status gsm_match(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, uint64_t *count,
+                     int32_t *rows, uint64_t rows_cap, uint64_t *rows_written) {
+  const auto t0 = std::chrono::steady_clock::now();
+  try {
+    if (!g || !qh || !count) {
+      gsm::set_error("gsm_match: NULL argument");
+      return GSM_E_INVALID_ARG;
+    }
+    const gsm::Options o = gsm::read_opts(opts, qh->q);
+    std::lock_guard<std::mutex> lk(g->mu);
+    gsm::Workspace &ws = gsm::acquire_ws(*g);
+    gsm::Matcher m(*g, *qh, o, ws);
+    m.rows_user = rows;
+    m.rows_cap = rows ? rows_cap : 0;
+    m.emit_host = (o.emit != nullptr) || (rows != nullptr && !o.rows_dev);
+    m.plan_capacity();
+    const uint64_t c = m.run();
+    m.sync();
+    m.finish_stats(c);
+    *count = c;
+    const uint64_t written = rows ? std::min(c, rows_cap) : 0;
+    if (rows_written) *rows_written = written;
+    if (o.stats) {
+      m.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      const uint32_t sz = std::min<uint32_t>(o.stats->struct_size ? o.stats->struct_size : sizeof(gsm_stats),
+                                             sizeof(gsm_stats));
+      std::memcpy(o.stats, &m.st, sz);
+      o.stats->struct_size = sz;
+    }
+    if (m.cancelled) {
+      gsm::set_error("emit callback stopped the match");
+      return GSM_E_CANCELLED;
+    }
+    if (rows && c > rows_cap) {
+      gsm::set_error("count exceeds rows_cap; first rows_cap rows written");
+      return GSM_E_TRUNCATED;
+    }
+    return GSM_OK;
+  } catch (const Error &e) {
+    gsm::set_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc &) {
+    gsm::set_error("host allocation failed");
+    return GSM_E_OOM;
+  }
+}
+
+gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query_t *qs,
+                           const gsm_match_opts *opts, uint64_t *counts) {
+  if (!g || nq < 0 || (nq > 0 && (!qs || !counts))) {
+    gsm::set_error("gsm_match_batch: invalid arguments");
+    return GSM_E_INVALID_ARG;
+  }
+  for (int32_t k = 0; k < nq; ++k) {
+    gsm_status st = gsm_match(g, qs[k], opts, &counts[k], nullptr, 0, nullptr);
+    if (st != GSM_OK) return st;
+  }
+  return GSM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,291 @@
+"""Python binding of libgsm (include/gsm.h): argument marshalling only.
+
+Every step of matching runs in the HIP library; this module converts numpy
+arrays and torch tensors into the C ABI's pointers and sizes.  torch is used
+for device buffers and streams when the caller passes device tensors.  If the
+library is missing it is built; if it cannot be loaded, an error is raised:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libgsm.so")
+_lib = None
+
+MAXQ = 16
+GRAPH_VALIDATE = 1
+GRAPH_DEVICE_PTRS = 2
+
+STATUS = {0: "GSM_OK", 1: "GSM_E_INVALID_ARG", 2: "GSM_E_BAD_GRAPH", 3: "GSM_E_BAD_QUERY",
+          4: "GSM_E_OOM", 5: "GSM_E_BUDGET", 6: "GSM_E_DEVICE", 7: "GSM_E_TRUNCATED",
+          8: "GSM_E_CANCELLED", 9: "GSM_E_UNSUPPORTED", 10: "GSM_E_TIMEOUT"}
+
+
+class GsmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("order", ctypes.c_int32 * MAXQ),
+                ("parent", ctypes.c_int32 * MAXQ), ("backmask", ctypes.c_uint32 * MAXQ)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("q", ctypes.c_int32),
+                ("candidates_root", ctypes.c_uint64), ("rows", ctypes.c_uint64 * MAXQ),
+                ("pairs", ctypes.c_uint64 * MAXQ), ("chunks", ctypes.c_uint64 * MAXQ),
+                ("probes", ctypes.c_uint64), ("alg_bytes", ctypes.c_uint64),
+                ("filter_bytes", ctypes.c_uint64), ("expand_launches", ctypes.c_uint64),
+                ("ms_expand", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        q = self.q
+        return {"q": q, "candidates_root": self.candidates_root,
+                "rows": list(self.rows[:q]), "pairs": list(self.pairs[:q]),
+                "chunks": list(self.chunks[:q]), "probes": self.probes,
+                "alg_bytes": self.alg_bytes, "filter_bytes": self.filter_bytes,
+                "expand_launches": self.expand_launches, "ms_expand": self.ms_expand,
+                "ms_total": self.ms_total}
+
+
+EMIT_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                           ctypes.c_uint64, ctypes.c_int32)
+
+
+class MatchOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("memory_budget_bytes", ctypes.c_uint64),
+                ("filter_rounds", ctypes.c_int32), ("use_degree", ctypes.c_int32),
+                ("use_ne", ctypes.c_int32), ("rows_on_device", ctypes.c_int32),
+                ("hip_stream", ctypes.c_void_p), ("root_qvertex", ctypes.c_int32),
+                ("root_mod", ctypes.c_uint32), ("root_rem", ctypes.c_uint32),
+                ("emit", EMIT_FN), ("emit_ctx", ctypes.c_void_p),
+                ("stats", ctypes.POINTER(Stats)), ("tile_items", ctypes.c_int32),
+                ("wg_size", ctypes.c_int32), ("profile", ctypes.c_int32)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import _build
+        _build.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i64, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
+    P = ctypes.POINTER
+    lib.gsm_status_str.restype = ctypes.c_char_p
+    lib.gsm_status_str.argtypes = [ctypes.c_int]
+    lib.gsm_last_error.restype = ctypes.c_char_p
+    lib.gsm_last_error.argtypes = []
+    lib.gsm_graph_create.restype = ctypes.c_int
+    lib.gsm_graph_create.argtypes = [i64, vp, vp, vp, u32, P(vp)]
+    lib.gsm_graph_destroy.argtypes = [vp]
+    lib.gsm_graph_info.restype = ctypes.c_int
+    lib.gsm_graph_info.argtypes = [vp, P(i64), P(i64), P(i32), P(i64)]
+    lib.gsm_query_create.restype = ctypes.c_int
+    lib.gsm_query_create.argtypes = [i32, i32, vp, vp, P(vp)]
+    lib.gsm_query_destroy.argtypes = [vp]
+    lib.gsm_query_plan.restype = ctypes.c_int
+    lib.gsm_query_plan.argtypes = [vp, vp, P(PlanInfo)]
+    lib.gsm_match_opts_init.argtypes = [P(MatchOpts)]
+    lib.gsm_filter.restype = ctypes.c_int
+    lib.gsm_filter.argtypes = [vp, vp, P(MatchOpts), vp]
+    lib.gsm_match.restype = ctypes.c_int
+    lib.gsm_match.argtypes = [vp, vp, P(MatchOpts), P(u64), vp, u64, P(u64)]
+    lib.gsm_match_batch.restype = ctypes.c_int
+    lib.gsm_match_batch.argtypes = [vp, i32, P(vp), P(MatchOpts), P(u64)]
+    _lib = lib
+    return lib
+
+
+def _check(st: int, allow=()):
+    if st != 0 and st not in allow:
+        raise GsmError(st, _load().gsm_last_error().decode())
+    return st
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+class Graph:
+    """A data graph uploaded to the device (simple, undirected, sorted CSR)."""
+
+    def __init__(self, row_ptr, col, labels=None, validate: bool = False):
+        lib = _load()
+        flags = GRAPH_VALIDATE if validate else 0
+        self._h = ctypes.c_void_p()
+        if hasattr(row_ptr, "data_ptr"):  # torch tensors on the device
+            flags |= GRAPH_DEVICE_PTRS
+            n = int(row_ptr.shape[0]) - 1
+            _check(lib.gsm_graph_create(n, ctypes.c_void_p(row_ptr.data_ptr()),
+                                        ctypes.c_void_p(col.data_ptr()),
+                                        None if labels is None else ctypes.c_void_p(labels.data_ptr()),
+                                        flags, ctypes.byref(self._h)))
+        else:
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            cl = np.ascontiguousarray(col, dtype=np.int32)
+            lb = None if labels is None else np.ascontiguousarray(labels, dtype=np.int32)
+            n = int(rp.shape[0]) - 1
+            _check(lib.gsm_graph_create(n, _p(rp), _p(cl), _p(lb), flags, ctypes.byref(self._h)))
+        self.n = n
+
+    @classmethod
+    def from_workload(cls, g, validate: bool = False):
+        return cls(g.row_ptr, g.col, g.labels, validate)
+
+    def info(self):
+        n, nnz, ml, md = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _check(_load().gsm_graph_info(self._h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(ml),
+                                      ctypes.byref(md)))
+        return {"n": n.value, "nnz": nnz.value, "max_label": ml.value, "max_degree": md.value}
+
+    def close(self):
+        if self._h:
+            _load().gsm_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Query:
+    """A connected query graph (1..16 vertices)."""
+
+    def __init__(self, q: int, edges, labels=None):
+        lib = _load()
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+        lb = None if labels is None else np.ascontiguousarray(labels, dtype=np.int32)
+        self._h = ctypes.c_void_p()
+        _check(lib.gsm_query_create(int(q), int(e.shape[0]), _p(e), _p(lb), ctypes.byref(self._h)))
+        self.q = int(q)
+
+    @classmethod
+    def from_workload(cls, qr):
+        return cls(qr.q, qr.edges, qr.labels)
+
+    def close(self):
+        if self._h:
+            _load().gsm_query_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_opts(budget: int = 0, filter_rounds: int = 1, use_degree: bool = True, use_ne: bool = True,
+              stream=None, root=None, tile_items: int = 0, wg_size: int = 0, profile: bool = False,
+              stats: Optional[Stats] = None) -> MatchOpts:
+    o = MatchOpts()
+    _load().gsm_match_opts_init(ctypes.byref(o))
+    o.memory_budget_bytes = int(budget)
+    o.filter_rounds = int(filter_rounds)
+    o.use_degree = 1 if use_degree else 0
+    o.use_ne = 1 if use_ne else 0
+    if stream is not None:
+        o.hip_stream = ctypes.c_void_p(int(stream))
+    if root is not None:
+        o.root_qvertex, o.root_mod, o.root_rem = int(root[0]), int(root[1]), int(root[2])
+    o.tile_items = int(tile_items)
+    o.wg_size = int(wg_size)
+    o.profile = 1 if profile else 0
+    if stats is not None:
+        stats.struct_size = ctypes.sizeof(Stats)
+        o.stats = ctypes.pointer(stats)
+    return o
+
+
+def plan(graph: Graph, query: Query):
+    info = PlanInfo()
+    _check(_load().gsm_query_plan(graph._h, query._h, ctypes.byref(info)))
+    q = info.q
+    return list(info.order[:q]), list(info.parent[:q]), list(info.backmask[:q])
+
+
+def filter(graph: Graph, query: Query, **kw) -> np.ndarray:
+    out = np.zeros(graph.n, dtype=np.uint16)
+    o = make_opts(**kw)
+    _check(_load().gsm_filter(graph._h, query._h, ctypes.byref(o), _p(out)))
+    return out
+
+
+def match(graph: Graph, query: Query, rows=None, rows_cap: Optional[int] = None, emit=None,
+          emit_device=None, **kw):
+    """Count (and list) embeddings.
+
+    rows: None (count only), "host" (a numpy array of rows_cap rows), or a
+    device torch int32 tensor of shape (cap, q).  emit: callable(rows ndarray)
+    per output chunk (host rows).  emit_device: callable(device_ptr, nrows, q)
+    per output chunk, rows left in device memory.  A callback returning a true
+    value stops the match.  Returns (count, rows_or_None, stats dict).
+    """
+    lib = _load()
+    st = Stats()
+    o = make_opts(stats=st, **kw)
+    cnt = ctypes.c_uint64(0)
+    written = ctypes.c_uint64(0)
+    out = None
+    ptr, cap = None, 0
+    keep = []
+    if emit_device is not None:
+        def _cbd(ctx, rp, nrows, q):
+            return 1 if emit_device(ctypes.cast(rp, ctypes.c_void_p).value, int(nrows), int(q)) else 0
+        cb = EMIT_FN(_cbd)
+        keep.append(cb)
+        o.emit = cb
+        o.rows_on_device = 1
+    elif emit is not None:
+        def _cb(ctx, rp, nrows, q):
+            a = np.ctypeslib.as_array(rp, shape=(int(nrows) * int(q),)).reshape(-1, int(q)).copy()
+            return 1 if emit(a) else 0
+        cb = EMIT_FN(_cb)
+        keep.append(cb)
+        o.emit = cb
+    elif isinstance(rows, str) and rows == "host":
+        if rows_cap is None:
+            raise ValueError("rows_cap is required for host rows")
+        out = np.zeros((int(rows_cap), query.q), dtype=np.int32)
+        ptr, cap = _p(out), int(rows_cap)
+    elif rows is not None:
+        if not (hasattr(rows, "is_cuda") and rows.is_cuda):
+            raise ValueError("rows must be 'host' or a device torch tensor")
+        o.rows_on_device = 1
+        out = rows
+        ptr, cap = ctypes.c_void_p(rows.data_ptr()), int(rows.shape[0])
+        if o.hip_stream is None:
+            import torch
+            o.hip_stream = ctypes.c_void_p(torch.cuda.current_stream(rows.device).cuda_stream)
+    status = lib.gsm_match(graph._h, query._h, ctypes.byref(o), ctypes.byref(cnt), ptr, cap,
+                           ctypes.byref(written))
+    _check(status, allow=(7,))
+    count = int(cnt.value)
+    if isinstance(out, np.ndarray):
+        out = out[:int(written.value)]
+    return count, out, st.as_dict()
+
+
+def match_batch(graph: Graph, queries: Sequence[Query], **kw) -> np.ndarray:
+    counts = np.zeros(len(queries), dtype=np.uint64)
+    arr = (ctypes.c_void_p * max(1, len(queries)))(*[q._h for q in queries])
+    o = make_opts(**kw)
+    _check(_load().gsm_match_batch(graph._h, len(queries), arr, ctypes.byref(o),
+                                   counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    return counts
