@@ -79,6 +79,13 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
+    # One HIP runtime per process: torch ships its own libamdhip64 (same
+    # soname); loading it first makes libgsm bind to it, so device pointers
+    # and streams from torch are valid in the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(_LIB_PATH):
         from . import _build
         _build.build()

@@ -177,7 +177,7 @@ def test_device_rows_truncation_and_emit(small):
     def sink(ptr, nrows, q):
         buf = torch.empty((nrows, q), dtype=torch.int32)
         import ctypes
-        lib = ctypes.CDLL("libamdhip64.so")
+        lib = ctypes.CDLL("libamdhip64.so.7")  # the runtime already loaded (by soname)
         lib.hipMemcpy(ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(ptr),
                       ctypes.c_size_t(nrows * q * 4), 2)
         seen.append(buf.numpy().copy())
