@@ -192,6 +192,14 @@ gsm_status gsm_match(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, 
                      int32_t *rows, uint64_t rows_cap, uint64_t *rows_written);
 
 /*
+ * The smallest memory_budget_bytes gsm_match accepts for qh on g: the first
+ * frontier (up to n rows), the candidate masks, and one row of every further
+ * level (and of the output staging buffer when rows go to the host).
+ *   host_rows  non-zero when rows will be delivered through host memory
+ */
+gsm_status gsm_match_min_budget(gsm_graph_t g, gsm_query_t qh, int32_t host_rows, uint64_t *bytes);
+
+/*
  * Counts the embeddings of nq queries on one graph in one pass of
  * level-synchronous batched launches (queries of different sizes and levels
  * share every launch; sizes stay on the device, so the whole pass is one

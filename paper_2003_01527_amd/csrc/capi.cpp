@@ -34,6 +34,31 @@ void DevBuf::release() {
   bytes = 0;
 }
 
+// Label-grouped copy of the adjacency: each row stably partitioned by
+// neighbour label (ids stay ascending inside a label), and per-row offsets of
+// every label.  Built once per graph for labelled graphs with few labels.
+void build_label_table(gsm_graph &g, const int64_t *rp, const int32_t *col, const int32_t *lab) {
+  const int32_t L = g.max_label + 1;
+  if (!lab || L > kMaxTableLabels || g.n == 0) return;
+  const int32_t stride = L + 1;
+  std::vector<uint32_t> off((size_t)g.n * stride);
+  std::vector<int32_t> cl((size_t)std::max<int64_t>(g.nnz, 1));
+  std::vector<uint32_t> cnt(stride);
+  for (int64_t v = 0; v < g.n; ++v) {
+    std::fill(cnt.begin(), cnt.end(), 0u);
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k) cnt[lab[col[k]] + 1]++;
+    for (int32_t l = 0; l < L; ++l) cnt[l + 1] += cnt[l];
+    uint32_t *o = off.data() + (size_t)v * stride;
+    for (int32_t l = 0; l <= L; ++l) o[l] = cnt[l];
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k) cl[rp[v] + cnt[lab[col[k]]]++] = col[k];
+  }
+  GSM_HIP(hipMalloc((void **)&g.col_lab, cl.size() * sizeof(int32_t)));
+  GSM_HIP(hipMemcpy(g.col_lab, cl.data(), cl.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  GSM_HIP(hipMalloc((void **)&g.loff, off.size() * sizeof(uint32_t)));
+  GSM_HIP(hipMemcpy(g.loff, off.data(), off.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  g.loff_stride = stride;
+}
+
 Workspace::Workspace() {
   counters.reserve(64 * sizeof(uint64_t));
   scan_scratch.reserve(scan_scratch_elems() * sizeof(uint64_t));
@@ -147,7 +172,7 @@ gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *co
       gsm::set_error("row_ptr[n] < 0");
       return GSM_E_BAD_GRAPH;
     }
-    if (flags & GSM_GRAPH_VALIDATE) {
+    if ((flags & GSM_GRAPH_VALIDATE) || labels) {
       h_col_store.resize(nnz);
       if (nnz)
         GSM_HIP(hipMemcpy(h_col_store.data(), col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -210,6 +235,7 @@ gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *co
     g->deg_ge.assign((size_t)maxd + 2, 0);
     for (int64_t v = 0; v < n; ++v) g->deg_ge[h_rp[v + 1] - h_rp[v]]++;
     for (int64_t d = maxd; d >= 0; --d) g->deg_ge[d] += g->deg_ge[d + 1];
+    gsm::build_label_table(*g, h_rp, h_col, h_lab);
     g->nheavy = (int64_t)heavy.size();
     if (!heavy.empty()) {
       GSM_HIP(hipMalloc((void **)&g->heavy, heavy.size() * sizeof(int32_t)));
@@ -235,6 +261,8 @@ void gsm_graph_destroy(gsm_graph_t g) {
   (void)hipFree(g->deg);
   (void)hipFree(g->ne0);
   (void)hipFree(g->heavy);
+  (void)hipFree(g->col_lab);
+  (void)hipFree(g->loff);
   delete g;
 }
 

@@ -67,6 +67,12 @@ struct gsm_graph {
   uint64_t *ne0 = nullptr;   // n: sum over neighbours of (label+1); null when unlabelled
   int32_t *heavy = nullptr;  // vertices with degree > kHeavyDegree
   int64_t nheavy = 0;
+  // label-grouped adjacency (labelled graphs with at most kMaxTableLabels labels):
+  // row v of col_lab holds v's neighbours sorted by (label, id), and
+  // loff[v * loff_stride + l] is where label l starts inside that row.
+  int32_t *col_lab = nullptr;
+  uint32_t *loff = nullptr;
+  int32_t loff_stride = 0;  // labels + 1, or 0 when there is no table
   // host statistics for the planner
   std::vector<int64_t> label_count;  // vertices per label
   std::vector<int64_t> deg_ge;       // deg_ge[d] = #vertices with degree >= d (d <= max_degree+1)
@@ -84,6 +90,7 @@ struct gsm_query {
 namespace gsm {
 
 constexpr int64_t kHeavyDegree = 2048;
+constexpr int32_t kMaxTableLabels = 64;
 
 // ------------------------------------------------------------------- plan --
 
@@ -119,6 +126,7 @@ struct LevelArgs {
   uint32_t nbr_mask;       // positions j < i adjacent to position i
   uint32_t qbit;           // cmask bit (query id) of position i
   uint32_t next_nbr_mask;  // positions j <= i adjacent to position i+1 (0 at the last level)
+  int32_t next_label;      // label of position i+1
   int32_t out_col[kMaxQ];  // emit: output column (query id) of position j
 };
 
@@ -126,10 +134,13 @@ struct LevelArgs {
 
 struct DeviceGraph {
   const int64_t *rp;
-  const int32_t *col;
+  const int32_t *col;      // rows sorted by id (membership tests)
   const int32_t *lab;
   const uint32_t *deg;
   const uint64_t *ne0;
+  const int32_t *gather;   // rows the expansion reads: col_lab when the table exists, else col
+  const uint32_t *loff;    // label offsets per row, or null
+  int32_t loff_stride;
   int64_t n;
 };
 
@@ -138,11 +149,14 @@ void launch_graph_stats(const gsm_graph &g, hipStream_t s);
 void launch_filter_init(const DeviceGraph &g, const QueryArgs &qa, uint16_t *cmask, hipStream_t s);
 void launch_filter_refine(const DeviceGraph &g, const int32_t *heavy, int64_t nheavy,
                           const QueryArgs &qa, const uint16_t *prev, uint16_t *next, hipStream_t s);
-// F1: vertices with bit `qbit` set (and degree >= 1 when need_edge); writes rows, W, counter.
-void launch_compact_first(const DeviceGraph &g, const uint16_t *cmask, uint32_t qbit, int need_edge,
-                          int32_t *rows, uint32_t *W, uint8_t *apos, uint64_t *counter,
-                          int32_t *emit_rows, uint64_t emit_cap, int32_t out_col0,
+// F1: vertices with bit `qbit` set.  With rows != null, also the neighbour
+// range of label next_label (W, abase), dropping vertices whose range is empty.
+// With emit_rows, writes the vertices as one-column rows (capped).
+void launch_compact_first(const DeviceGraph &g, const uint16_t *cmask, uint32_t qbit,
+                          int32_t next_label, int32_t *rows, uint32_t *W, int64_t *abase,
+                          uint8_t *apos, uint64_t *counter, int32_t *emit_rows, uint64_t emit_cap,
                           hipStream_t s);
+void build_label_table(gsm_graph &g, const int64_t *h_rp, const int32_t *h_col, const int32_t *h_lab);
 // S[0..N] = exclusive scan of W[0..N-1]; N read from device *n_dev; scratch >= scan_scratch_bytes()
 size_t scan_scratch_elems();
 void launch_scan(const uint32_t *W, const uint64_t *n_dev, uint64_t *S, uint64_t *total_out,
@@ -153,15 +167,17 @@ enum ExpandMode { kModeNext = 0, kModeCount = 1, kModeEmit = 2 };
 struct ExpandArgs {
   DeviceGraph g;
   const uint16_t *cmask;
-  const int32_t *rows_in;  // N x i
-  const uint8_t *apos_in;  // N
-  const uint64_t *S;       // N+1
+  const int32_t *rows_in;   // N x i
+  const uint8_t *apos_in;   // N: anchor position
+  const int64_t *abase_in;  // N: first gather index of the row's pair range
+  const uint64_t *S;        // N+1
   uint64_t n_rows;         // N
   uint64_t pair_begin, pair_end;
   // kModeNext outputs
   int32_t *rows_out;  // x (i+1)
   uint32_t *W_out;
   uint8_t *apos_out;
+  int64_t *abase_out;
   // shared counter: rows written (next) / embeddings counted (count, emit)
   uint64_t *counter;
   uint64_t *probes;  // binary-search steps of the back-edge checks
@@ -169,6 +185,7 @@ struct ExpandArgs {
   int32_t *emit_rows;  // x q, query-id columns
   uint64_t emit_base;  // rows already emitted before this launch (for the cap)
   uint64_t emit_cap;
+  int32_t staged;  // output rows pass through LDS (dynamic shared memory)
   LevelArgs L;
 };
 
@@ -178,7 +195,7 @@ void launch_expand(const ExpandArgs &a, int mode, int wg, int items, hipStream_t
 
 struct Workspace {
   DevBuf cmask, cmask2;
-  DevBuf rows[kMaxQ], W[kMaxQ], apos[kMaxQ], S[kMaxQ];
+  DevBuf rows[kMaxQ], W[kMaxQ], apos[kMaxQ], abase[kMaxQ], S[kMaxQ];
   DevBuf counters;  // kMaxQ + 8 uint64
   DevBuf scan_scratch;
   DevBuf emit;      // staging for host-bound rows

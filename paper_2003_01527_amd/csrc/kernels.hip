@@ -199,11 +199,29 @@ __global__ __launch_bounds__(256) void k_refine_heavy(DeviceGraph g, QueryArgs q
 
 // ------------------------------------------------------ first frontier --
 
+// Neighbour range of x that holds label l: [base, base + size) in g.gather.
+__device__ __forceinline__ uint32_t label_range(const DeviceGraph &g, int32_t x, int32_t l,
+                                                int64_t &base) {
+  const int64_t b = g.rp[x];
+  if (g.loff) {
+    const uint32_t *o = g.loff + (int64_t)x * g.loff_stride;
+    if (l + 1 >= g.loff_stride) {  // label absent from the graph
+      base = b;
+      return 0;
+    }
+    const uint32_t lo = o[l], hi = o[l + 1];
+    base = b + lo;
+    return hi - lo;
+  }
+  base = b;
+  return g.deg[x];
+}
+
 __global__ __launch_bounds__(256) void k_compact_first(DeviceGraph g, const uint16_t *cmask,
-                                                       uint32_t qbit, int need_edge, int32_t *rows,
-                                                       uint32_t *W, uint8_t *apos,
-                                                       uint64_t *counter, int32_t *emit_rows,
-                                                       uint64_t emit_cap, int32_t out_col0) {
+                                                       uint32_t qbit, int32_t next_label,
+                                                       int32_t *rows, uint32_t *W, int64_t *abase,
+                                                       uint8_t *apos, uint64_t *counter,
+                                                       int32_t *emit_rows, uint64_t emit_cap) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   // every lane of the wave runs the same number of iterations
@@ -212,24 +230,29 @@ __global__ __launch_bounds__(256) void k_compact_first(DeviceGraph g, const uint
     const int64_t v = vb + (threadIdx.x & (kWave - 1));
     bool keep = false;
     uint32_t d = 0;
+    int64_t b = 0;
     if (v < g.n) {
-      d = g.deg[v];
-      keep = ((cmask[v] >> qbit) & 1) && (!need_edge || d > 0);
+      keep = (cmask[v] >> qbit) & 1;
+      if (keep && rows) {
+        d = label_range(g, (int32_t)v, next_label, b);
+        keep = d > 0;  // no neighbour can take the next query vertex
+      }
     }
     const uint64_t mask = wave_ballot(keep);
     if (mask == 0) continue;
     uint64_t base = 0;
-    if ((threadIdx.x & (kWave - 1)) == 0) base = atomicAdd((unsigned long long *)counter, (unsigned long long)__popcll(mask));
+    if ((threadIdx.x & (kWave - 1)) == 0)
+      base = atomicAdd((unsigned long long *)counter, (unsigned long long)__popcll(mask));
     base = __shfl(base, 0, kWave);
     if (keep) {
       const uint64_t pos = base + lane_prefix(mask);
       if (rows) {
         rows[pos] = (int32_t)v;
         W[pos] = d;
+        abase[pos] = b;
         apos[pos] = 0;
       }
       if (emit_rows && pos < emit_cap) emit_rows[pos] = (int32_t)v;
-      (void)out_col0;
     }
   }
 }
@@ -308,22 +331,30 @@ __global__ __launch_bounds__(kScanWG) void k_scan_down(const uint32_t *W, const 
 // --------------------------------------------------------------- expand --
 //
 // One launch expands rows of level i over a range of the flat pair space.
-// Pair t belongs to row r with S[r] <= t < S[r+1]; its candidate is the
-// (t - S[r])-th neighbour of the row's anchor (the earlier-matched neighbour
-// of the new query vertex with the smallest data degree, chosen when the row
-// was written).  Lanes of a wave take consecutive pairs, so neighbour reads
-// of one row are coalesced.  Survivors of the candidate-set test,
-// injectivity and every back-edge are compacted with a wave ballot, a
-// workgroup scan and one atomic per tile.
+// Pair t belongs to row r with S[r] <= t < S[r+1]; its candidate is
+// gather[abase[r] + t - S[r]]: a neighbour of the row's anchor (the earlier
+// matched neighbour of the new query vertex with the fewest neighbours of the
+// new vertex's label, chosen when the row was written) that carries that label.
+// Lanes of a wave take consecutive pairs, so neighbour reads of one row are
+// coalesced.  A candidate survives the candidate-mask test, injectivity and a
+// binary search for every other back-edge; when the row goes on to a further
+// level it must also leave a non-empty range for the next query vertex.
+// Survivors are compacted item by item (wave ballot, workgroup prefix, one
+// atomic per tile) so consecutive lanes write consecutive rows; rows are
+// staged in LDS and copied out with contiguous stores.
 template <int WG, int ITEMS, int MODE>
 __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
   constexpr int TILE = WG * ITEMS;
+  constexpr int NW = WG / kWave;
   __shared__ uint64_t sS[TILE + 1];
-  __shared__ uint64_t sw[WG / kWave];
-  __shared__ uint64_t s_r0, s_base;
+  __shared__ uint64_t sw[NW];
+  __shared__ uint32_t s_cnt[ITEMS * NW];
+  __shared__ uint64_t s_r0, s_base, s_total;
+  extern __shared__ int32_t s_out[];
 
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int i = a.L.i;
+  const int width = (MODE == kModeNext) ? i + 1 : a.L.q;
   const uint64_t npairs = a.pair_end - a.pair_begin;
   const uint64_t ntiles = (npairs + TILE - 1) / TILE;
   const uint32_t G = gridDim.x, b = blockIdx.x;
@@ -359,10 +390,16 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
     uint32_t keepbits = 0;
     int32_t wv[ITEMS];
     uint32_t rk[ITEMS];
+    uint32_t nW[ITEMS];
+    int64_t nbase[ITEMS];
+    uint8_t napos[ITEMS];
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
       wv[it] = 0;
       rk[it] = 0;
+      nW[it] = 0;
+      nbase[it] = 0;
+      napos[it] = 0;
       const uint64_t t = t0 + (uint64_t)it * WG + tid;
       if (t >= t1) continue;
       int lo = 0, hi = TILE;  // sS[lo] <= t < sS[hi]
@@ -376,8 +413,7 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
       const uint64_t r = r0 + lo;
       const int32_t *row = a.rows_in + r * (uint64_t)i;
       const int ap = a.apos_in[r];
-      const int32_t anc = row[ap];
-      const int32_t w = a.g.col[a.g.rp[anc] + (int64_t)(t - sS[lo])];
+      const int32_t w = a.g.gather[a.abase_in[r] + (int64_t)(t - sS[lo])];
       bool keep = (a.cmask[w] >> a.L.qbit) & 1;
       uint32_t m = inj_mask;
       while (keep && m) {
@@ -391,6 +427,28 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
         m &= m - 1;
         keep = has_edge(a.g, row[j], w, probes);
       }
+      if (MODE == kModeNext && keep) {
+        // anchor of the next position: the earlier neighbour with the fewest
+        // neighbours of the next label; an empty range ends the row here
+        uint32_t mm = a.L.next_nbr_mask, best = 0xffffffffu;
+        int bj = 0;
+        int64_t bb = 0;
+        while (mm) {
+          const int j = __builtin_ctz(mm);
+          mm &= mm - 1;
+          int64_t base;
+          const uint32_t d = label_range(a.g, j == i ? w : row[j], a.L.next_label, base);
+          if (d < best) {
+            best = d;
+            bj = j;
+            bb = base;
+          }
+        }
+        keep = best > 0;
+        nW[it] = best;
+        nbase[it] = bb;
+        napos[it] = (uint8_t)bj;
+      }
       if (keep) {
         keepbits |= 1u << it;
         wv[it] = w;
@@ -398,49 +456,82 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
       }
     }
 
-    const uint32_t c = __builtin_popcount(keepbits);
     if (MODE == kModeCount) {
-      wg_count += c;
+      wg_count += __builtin_popcount(keepbits);
       continue;
     }
-    uint64_t total;
-    const uint64_t off = block_excl_scan<WG>(c, sw, &total);
-    if (tid == 0) s_base = total ? atomicAdd((unsigned long long *)a.counter, (unsigned long long)total) : 0;
-    __syncthreads();
-    uint64_t pos = s_base + off;
+    // item-major compaction: survivors of item 0 of every lane, then item 1, ...
+    uint32_t lofs[ITEMS];
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
+      const uint64_t mask = wave_ballot((keepbits >> it) & 1);
+      lofs[it] = lane_prefix(mask);
+      if (lane == 0) s_cnt[it * NW + wid] = (uint32_t)__popcll(mask);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t tot = 0;
+      for (int k = 0; k < ITEMS * NW; ++k) tot += s_cnt[k];
+      s_total = tot;
+      s_base = tot ? atomicAdd((unsigned long long *)a.counter, (unsigned long long)tot) : 0;
+    }
+    __syncthreads();
+    const uint64_t total = s_total, base = s_base;
+    if (total == 0) continue;
+    uint32_t before = 0;  // survivors ahead of this lane's item `it`
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      uint32_t pre = before;
+      for (int w2 = 0; w2 < wid; ++w2) pre += s_cnt[it * NW + w2];
+      for (int w2 = 0; w2 < NW; ++w2) before += s_cnt[it * NW + w2];
       if (!((keepbits >> it) & 1)) continue;
-      const uint64_t r = r0 + rk[it];
-      const int32_t *row = a.rows_in + r * (uint64_t)i;
+      const uint32_t loc = pre + lofs[it];
+      const uint64_t pos = base + loc;
+      const int32_t *row = a.rows_in + (r0 + rk[it]) * (uint64_t)i;
       const int32_t w = wv[it];
       if (MODE == kModeNext) {
-        int32_t *o = a.rows_out + pos * (uint64_t)(i + 1);
-        for (int j = 0; j < i; ++j) o[j] = row[j];
-        o[i] = w;
-        // anchor of the next position: earlier neighbour with the smallest degree
-        uint32_t m = a.L.next_nbr_mask, best = 0xffffffffu;
-        int bj = 0;
-        while (m) {
-          const int j = __builtin_ctz(m);
-          m &= m - 1;
-          const uint32_t d = a.g.deg[j == i ? w : row[j]];
-          if (d < best) {
-            best = d;
-            bj = j;
-          }
+        a.W_out[pos] = nW[it];
+        a.abase_out[pos] = nbase[it];
+        a.apos_out[pos] = napos[it];
+        if (a.staged) {
+          int32_t *o = s_out + (uint64_t)loc * width;
+          for (int j = 0; j < i; ++j) o[j] = row[j];
+          o[i] = w;
+        } else {
+          int32_t *o = a.rows_out + pos * (uint64_t)width;
+          for (int j = 0; j < i; ++j) o[j] = row[j];
+          o[i] = w;
         }
-        a.W_out[pos] = best;
-        a.apos_out[pos] = (uint8_t)bj;
-      } else {  // kModeEmit
-        const uint64_t slot = pos - a.emit_base;
-        if (slot < a.emit_cap) {
-          int32_t *o = a.emit_rows + slot * (uint64_t)a.L.q;
+      } else {  // kModeEmit: rows in query-id columns
+        if (a.staged) {
+          int32_t *o = s_out + (uint64_t)loc * width;
           for (int j = 0; j < i; ++j) o[a.L.out_col[j]] = row[j];
           o[a.L.out_col[i]] = w;
+        } else {
+          const uint64_t slot = pos - a.emit_base;
+          if (slot < a.emit_cap) {
+            int32_t *o = a.emit_rows + slot * (uint64_t)width;
+            for (int j = 0; j < i; ++j) o[a.L.out_col[j]] = row[j];
+            o[a.L.out_col[i]] = w;
+          }
         }
       }
-      ++pos;
+    }
+    if (a.staged) {
+      __syncthreads();
+      // contiguous copy of the tile's rows
+      int32_t *dst;
+      uint64_t nints = total * (uint64_t)width;
+      if (MODE == kModeNext) {
+        dst = a.rows_out + base * (uint64_t)width;
+      } else {
+        const uint64_t slot0 = base - a.emit_base;
+        const uint64_t room = slot0 < a.emit_cap ? a.emit_cap - slot0 : 0;
+        if (room < total) nints = room * (uint64_t)width;
+        dst = a.emit_rows + slot0 * (uint64_t)width;
+      }
+      for (uint64_t k = tid; k < nints; k += WG) dst[k] = s_out[k];
+      __syncthreads();  // s_out is reused by the next tile
     }
   }
   if (MODE == kModeCount) {
@@ -455,8 +546,10 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
   }
 }
 
+constexpr size_t kMaxStageBytes = 32 * 1024;
+
 template <int WG, int ITEMS>
-void launch_expand_t(const ExpandArgs &a, int mode, hipStream_t s) {
+void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
   constexpr uint64_t TILE = (uint64_t)WG * ITEMS;
   const uint64_t ntiles = (a.pair_end - a.pair_begin + TILE - 1) / TILE;
   if (ntiles == 0) return;
@@ -464,15 +557,19 @@ void launch_expand_t(const ExpandArgs &a, int mode, hipStream_t s) {
   const uint64_t kMaxGrid = 1u << 20;
   if (grid > kMaxGrid) grid = kMaxGrid;
   if (grid >= 8) grid &= ~7ull;
+  const int width = (mode == kModeNext) ? a.L.i + 1 : a.L.q;
+  const size_t stage = TILE * (size_t)width * sizeof(int32_t);
+  a.staged = (mode != kModeCount && stage <= kMaxStageBytes) ? 1 : 0;
+  const size_t smem = a.staged ? stage : 0;
   switch (mode) {
     case kModeNext:
-      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeNext>), dim3((uint32_t)grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeNext>), dim3((uint32_t)grid), dim3(WG), smem, s, a);
       break;
     case kModeCount:
       hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeCount>), dim3((uint32_t)grid), dim3(WG), 0, s, a);
       break;
     default:
-      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeEmit>), dim3((uint32_t)grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeEmit>), dim3((uint32_t)grid), dim3(WG), smem, s, a);
       break;
   }
 }
@@ -524,12 +621,13 @@ void launch_filter_refine(const DeviceGraph &g, const int32_t *heavy, int64_t nh
   }
 }
 
-void launch_compact_first(const DeviceGraph &g, const uint16_t *cmask, uint32_t qbit, int need_edge,
-                          int32_t *rows, uint32_t *W, uint8_t *apos, uint64_t *counter,
-                          int32_t *emit_rows, uint64_t emit_cap, int32_t out_col0, hipStream_t s) {
+void launch_compact_first(const DeviceGraph &g, const uint16_t *cmask, uint32_t qbit,
+                          int32_t next_label, int32_t *rows, uint32_t *W, int64_t *abase,
+                          uint8_t *apos, uint64_t *counter, int32_t *emit_rows, uint64_t emit_cap,
+                          hipStream_t s) {
   if (g.n == 0) return;
   hipLaunchKernelGGL(k_compact_first, dim3(grid_for(g.n, 256, 1u << 14)), dim3(256), 0, s, g, cmask,
-                     qbit, need_edge, rows, W, apos, counter, emit_rows, emit_cap, out_col0);
+                     qbit, next_label, rows, W, abase, apos, counter, emit_rows, emit_cap);
   GSM_HIP(hipGetLastError());
 }
 

@@ -61,6 +61,22 @@ Options read_opts(const gsm_match_opts *o, int q) {
   return r;
 }
 
+// Device bytes that do not depend on the budget: two candidate masks, the
+// first frontier (at most n rows with range data) and its scan.
+uint64_t fixed_bytes(int64_t nv) {
+  const uint64_t n = (uint64_t)std::max<int64_t>(nv, 1);
+  return 2 * n * 2 + n * (4 + 4 + 8 + 1) + (n + 1) * 8 + 4096;
+}
+
+// Smallest budget for which every level (and the staging buffer) gets a row.
+uint64_t min_budget_bytes(int64_t nv, int q, bool host_rows) {
+  const int shares = std::max(0, q - 2) + (host_rows ? 1 : 0);
+  uint64_t per = 0;
+  for (int i = 2; i < q; ++i) per = std::max<uint64_t>(per, 4 * (uint64_t)i + 21);
+  if (host_rows) per = std::max<uint64_t>(per, 4 * (uint64_t)q);
+  return fixed_bytes(nv) + 64 + (uint64_t)shares * per;
+}
+
 struct Matcher {
   gsm_graph &g;
   const gsm_query &qh;
@@ -86,7 +102,8 @@ struct Matcher {
   Matcher(gsm_graph &g_, const gsm_query &q_, const Options &o_, Workspace &ws_)
       : g(g_), qh(q_), o(o_), ws(ws_), s(o_.stream) {
     p = make_plan(g, qh);
-    dg = DeviceGraph{g.rp, g.col, g.lab, g.deg, g.ne0, g.n};
+    dg = DeviceGraph{g.rp,  g.col,  g.lab, g.deg, g.ne0, g.col_lab ? g.col_lab : g.col,
+                     g.loff, g.loff_stride, g.n};
     dcnt = ws.counters.as<uint64_t>();
     std::memset(&st, 0, sizeof(st));
     st.struct_size = sizeof(st);
@@ -168,14 +185,14 @@ struct Matcher {
   // 2..q-1 plus the host staging buffer when rows go to the host.
   void plan_capacity() {
     const uint64_t n = (uint64_t)std::max<int64_t>(g.n, 1);
-    const uint64_t fixed = 2 * n * 2 + n * (4 + 4 + 1) + (n + 1) * 8 + 4096;
+    const uint64_t fixed = fixed_bytes(g.n);
     if (o.budget < fixed + 64) throw Error{GSM_E_BUDGET, "memory budget below the first frontier"};
     const uint64_t rest = o.budget - fixed;
     const int shares = std::max(0, p.q - 2) + (emit_host ? 1 : 0);
     for (int i = 0; i < kMaxQ; ++i) cap[i] = 0;
     cap[1] = n;
     for (int i = 2; i < p.q; ++i) {
-      cap[i] = rest / shares / (uint64_t)(4 * i + 13);
+      cap[i] = rest / shares / (uint64_t)(4 * i + 21);
       if (cap[i] < 1) throw Error{GSM_E_BUDGET, "memory budget below one row of level " + std::to_string(i)};
     }
     if (emit_host) {
@@ -188,6 +205,7 @@ struct Matcher {
       if (ws.S[i].bytes > (std::max<uint64_t>(cap[i], 1) + 1) * 8 + 256) ws.S[i].release();
       if (ws.W[i].bytes > std::max<uint64_t>(cap[i], 1) * 4 + 256) ws.W[i].release();
       if (ws.apos[i].bytes > std::max<uint64_t>(cap[i], 1) + 256) ws.apos[i].release();
+      if (ws.abase[i].bytes > std::max<uint64_t>(cap[i], 1) * 8 + 256) ws.abase[i].release();
     }
   }
 
@@ -195,6 +213,7 @@ struct Matcher {
     ws.rows[i].reserve(rows * 4 * (uint64_t)i);
     ws.W[i].reserve(rows * 4);
     ws.apos[i].reserve(rows);
+    ws.abase[i].reserve(rows * 8);
     ws.S[i].reserve((rows + 1) * 8);
   }
 
@@ -206,6 +225,7 @@ struct Matcher {
     L.nbr_mask = p.backmask[i];
     L.qbit = (uint32_t)p.order[i];
     L.next_nbr_mask = (i + 1 < p.q) ? p.backmask[i + 1] : 0;
+    L.next_label = (i + 1 < p.q) ? p.qlab[p.order[i + 1]] : 0;
     for (int j = 0; j < p.q; ++j) L.out_col[j] = p.order[j];
     return L;
   }
@@ -248,6 +268,7 @@ struct Matcher {
     a.cmask = ws.cmask.as<uint16_t>();
     a.rows_in = ws.rows[i].as<int32_t>();
     a.apos_in = ws.apos[i].as<uint8_t>();
+    a.abase_in = ws.abase[i].as<int64_t>();
     a.S = ws.S[i].as<uint64_t>();
     a.n_rows = N;
     a.L = level_args(i);
@@ -262,6 +283,7 @@ struct Matcher {
         a.rows_out = ws.rows[i + 1].as<int32_t>();
         a.W_out = ws.W[i + 1].as<uint32_t>();
         a.apos_out = ws.apos[i + 1].as<uint8_t>();
+        a.abase_out = ws.abase[i + 1].as<int64_t>();
         a.counter = dcnt + kCntRows + i + 1;
         expand(a, kModeNext);
         st.chunks[i]++;
@@ -319,8 +341,8 @@ struct Matcher {
           dcap = (uint64_t)g.n;
         }
       }
-      launch_compact_first(dg, ws.cmask.as<uint16_t>(), qbit0, 0, nullptr, nullptr, nullptr,
-                           dcnt + kCntResult, dst, dcap, 0, s);
+      launch_compact_first(dg, ws.cmask.as<uint16_t>(), qbit0, 0, nullptr, nullptr, nullptr, nullptr,
+                           dcnt + kCntResult, dst, dcap, s);
       fetch_counters();
       const uint64_t count = ws.h_counters[kCntResult];
       st.rows[0] = count;
@@ -329,9 +351,9 @@ struct Matcher {
       return count;
     }
     reserve_level(1, (uint64_t)std::max<int64_t>(g.n, 1));
-    launch_compact_first(dg, ws.cmask.as<uint16_t>(), qbit0, 1, ws.rows[1].as<int32_t>(),
-                         ws.W[1].as<uint32_t>(), ws.apos[1].as<uint8_t>(), dcnt + kCntRows + 1,
-                         nullptr, 0, 0, s);
+    launch_compact_first(dg, ws.cmask.as<uint16_t>(), qbit0, p.qlab[p.order[1]],
+                         ws.rows[1].as<int32_t>(), ws.W[1].as<uint32_t>(), ws.abase[1].as<int64_t>(),
+                         ws.apos[1].as<uint8_t>(), dcnt + kCntRows + 1, nullptr, 0, s);
     process_level(1);
     fetch_counters();
     st.candidates_root = st.rows[0];
@@ -341,15 +363,16 @@ struct Matcher {
   }
 
   // Algorithmic bytes of the expansion launches (what the method must move):
-  // per input row its ids, anchor position, scan entry and two offsets; per
-  // pair a neighbour id and a candidate-mask entry; per binary-search step
-  // one neighbour id plus two offsets per checked back-edge list (counted as
-  // 4 bytes a step); per written row its ids, weight and anchor position.
+  // per input row its ids, anchor position, range start and scan entry; per
+  // pair a neighbour id and a candidate-mask entry; per binary-search step one
+  // neighbour id (4 bytes); per written row its ids, range size, range start
+  // and anchor position plus two range offsets read to choose the anchor;
+  // per emitted embedding its q ids.
   void finish_stats(uint64_t count) {
     uint64_t b = 0;
     for (int i = 1; i < p.q; ++i) {
-      b += st.rows[i - 1] * (4ull * i + 1 + 8 + 16) + st.pairs[i] * (4 + 2);
-      if (i + 1 < p.q) b += st.rows[i] * (4ull * (i + 1) + 4 + 1);
+      b += st.rows[i - 1] * (4ull * i + 1 + 8 + 8) + st.pairs[i] * (4 + 2);
+      if (i + 1 < p.q) b += st.rows[i] * (4ull * (i + 1) + 4 + 8 + 1 + 16);
     }
     b += st.probes * 4;
     if (rows_user || o.emit) b += count * 4ull * p.q;
@@ -457,6 +480,20 @@ gsm_status gsm_match(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, 
   } catch (const std::bad_alloc &) {
     gsm::set_error("host allocation failed");
     return GSM_E_OOM;
+  }
+}
+
+gsm_status gsm_match_min_budget(gsm_graph_t g, gsm_query_t qh, int32_t host_rows, uint64_t *bytes) {
+  try {
+    if (!g || !qh || !bytes) {
+      gsm::set_error("gsm_match_min_budget: NULL argument");
+      return GSM_E_INVALID_ARG;
+    }
+    *bytes = gsm::min_budget_bytes(g->n, qh->q, host_rows != 0);
+    return GSM_OK;
+  } catch (const Error &e) {
+    gsm::set_error(e.msg);
+    return e.status;
   }
 }
 

@@ -111,6 +111,8 @@ def _load():
     lib.gsm_filter.argtypes = [vp, vp, P(MatchOpts), vp]
     lib.gsm_match.restype = ctypes.c_int
     lib.gsm_match.argtypes = [vp, vp, P(MatchOpts), P(u64), vp, u64, P(u64)]
+    lib.gsm_match_min_budget.restype = ctypes.c_int
+    lib.gsm_match_min_budget.argtypes = [vp, vp, i32, P(u64)]
     lib.gsm_match_batch.restype = ctypes.c_int
     lib.gsm_match_batch.argtypes = [vp, i32, P(vp), P(MatchOpts), P(u64)]
     _lib = lib
@@ -287,6 +289,12 @@ def match(graph: Graph, query: Query, rows=None, rows_cap: Optional[int] = None,
     if isinstance(out, np.ndarray):
         out = out[:int(written.value)]
     return count, out, st.as_dict()
+
+
+def min_budget(graph: Graph, query: Query, host_rows: bool = False) -> int:
+    b = ctypes.c_uint64(0)
+    _check(_load().gsm_match_min_budget(graph._h, query._h, 1 if host_rows else 0, ctypes.byref(b)))
+    return int(b.value)
 
 
 def match_batch(graph: Graph, queries: Sequence[Query], **kw) -> np.ndarray:

@@ -122,9 +122,8 @@ def test_powerlaw_slice_rows_and_tiny_budgets(powerlaw):
     root = (0, 128, 1)
     c, r = oracle.match(w.graph, qr, threads=NCPU, root=root)
     assert 0 < c < 5_000_000
-    n = w.graph.n
-    fixed = 2 * n * 2 + n * 9 + (n + 1) * 8 + 4096
-    for budget in (0, fixed + (1 << 16), fixed + 4096):
+    lo = gsm.min_budget(G, Q, host_rows=True)
+    for budget in (0, lo + (1 << 20), lo + (1 << 16)):
         cg, rg = gpu_rows(G, Q, root=root, budget=budget)
         assert cg == c, budget
         np.testing.assert_array_equal(rg, r)
@@ -166,9 +165,8 @@ def test_device_rows_truncation_and_emit(small):
     assert all(tuple(x) in rset for x in got.tolist())
     # host emit callback, chunked by a small budget
     chunks = []
-    n = w.graph.n
-    fixed = 2 * n * 2 + n * 9 + (n + 1) * 8 + 4096
-    cg, _, st = gsm.match(G, Q, emit=lambda a: chunks.append(a) and False, budget=fixed + 20_000)
+    lo = gsm.min_budget(G, Q, host_rows=True)
+    cg, _, st = gsm.match(G, Q, emit=lambda a: chunks.append(a) and False, budget=lo + 20_000)
     assert cg == c
     np.testing.assert_array_equal(oracle.sort_rows(np.concatenate(chunks)), r)
     # device emit callback sees every row once
@@ -182,7 +180,7 @@ def test_device_rows_truncation_and_emit(small):
                       ctypes.c_size_t(nrows * q * 4), 2)
         seen.append(buf.numpy().copy())
         return False
-    cg, _, _ = gsm.match(G, Q, emit_device=sink, budget=fixed + 20_000)
+    cg, _, _ = gsm.match(G, Q, emit_device=sink, budget=lo + 20_000)
     assert cg == c
     np.testing.assert_array_equal(oracle.sort_rows(np.concatenate(seen)), r)
 
@@ -203,6 +201,12 @@ def test_budget_error(small):
     with pytest.raises(gsm.GsmError) as ei:
         gsm.match(G, Q, budget=1024)
     assert ei.value.status == 5
+    lo = gsm.min_budget(G, Q)
+    with pytest.raises(gsm.GsmError) as ei:
+        gsm.match(G, Q, budget=lo - 100)
+    assert ei.value.status == 5
+    c, _ = oracle.match(w.graph, w.queries[0], rows=False)
+    assert gsm.match(G, Q, budget=lo)[0] == c
 
 
 def test_graph_validation_on_device_errors():
