@@ -45,7 +45,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--items", type=int, default=0)
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="only run a plain device-to-device copy of this many GiB (calibrates "
+                         "the HBM byte counters of rocprofv3) and exit")
     args = ap.parse_args()
+
+    if args.copy_gib > 0:
+        import torch
+        nbytes = int(args.copy_gib * (1 << 30))
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes}), flush=True)
+        return
 
     if args.gpus != 1:
         print("bench.py measures one GPU: the matcher runs on a single device "

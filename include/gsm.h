@@ -162,7 +162,11 @@ typedef struct gsm_match_opts {
   int32_t tile_items;           /* pairs per thread per tile: 1, 2, 4, 8 (0 = auto) */
   int32_t wg_size;              /* threads per workgroup: 128, 256, 512 (0 = auto) */
   int32_t profile;              /* time each expansion launch with HIP events into stats */
+  uint32_t flags;               /* GSM_MATCH_* tuning flags */
 } gsm_match_opts;
+
+/* Write output rows straight from registers instead of staging them in LDS. */
+#define GSM_MATCH_NO_OUTPUT_STAGING 1u
 
 /* Fills defaults (struct_size set, budget 0, rounds 1, degree and NE on, no slice). */
 void gsm_match_opts_init(gsm_match_opts *o);

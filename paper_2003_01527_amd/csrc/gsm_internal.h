@@ -185,7 +185,9 @@ struct ExpandArgs {
   int32_t *emit_rows;  // x q, query-id columns
   uint64_t emit_base;  // rows already emitted before this launch (for the cap)
   uint64_t emit_cap;
-  int32_t staged;  // output rows pass through LDS (dynamic shared memory)
+  int32_t staged;        // output rows pass through LDS (dynamic shared memory)
+  int32_t stage_in;      // the tile's input rows are copied to LDS
+  int32_t stage_out_ok;  // the caller allows output staging
   LevelArgs L;
 };
 

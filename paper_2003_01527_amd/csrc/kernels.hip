@@ -339,22 +339,31 @@ __global__ __launch_bounds__(kScanWG) void k_scan_down(const uint32_t *W, const 
 // coalesced.  A candidate survives the candidate-mask test, injectivity and a
 // binary search for every other back-edge; when the row goes on to a further
 // level it must also leave a non-empty range for the next query vertex.
-// Survivors are compacted item by item (wave ballot, workgroup prefix, one
-// atomic per tile) so consecutive lanes write consecutive rows; rows are
-// staged in LDS and copied out with contiguous stores.
+//
+// Per tile: the first wave finds the tile's first row by a 64-way search; the
+// rows the tile touches are copied to LDS with contiguous loads; every item's
+// loads are issued before any result is used, so a wave keeps ITEMS gathers
+// in flight.  Survivors are compacted item by item (wave ballot, workgroup
+// prefix, one atomic per tile) so consecutive lanes write consecutive rows;
+// output rows are staged in LDS and copied out with contiguous stores when
+// they fit.
 template <int WG, int ITEMS, int MODE>
 __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
   constexpr int TILE = WG * ITEMS;
   constexpr int NW = WG / kWave;
-  __shared__ uint64_t sS[TILE + 1];
+  __shared__ uint32_t sS[TILE + 1];  // row starts relative to the tile, clamped to TILE+1
   __shared__ uint64_t sw[NW];
   __shared__ uint32_t s_cnt[ITEMS * NW];
-  __shared__ uint64_t s_r0, s_base, s_total;
-  extern __shared__ int32_t s_out[];
+  __shared__ uint64_t s_r0, s_base;
+  __shared__ uint32_t s_total, s_R, s_lead;
+  extern __shared__ int32_t dyn[];  // [TILE * i] input rows, then [TILE * width] output rows
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int i = a.L.i;
   const int width = (MODE == kModeNext) ? i + 1 : a.L.q;
+  const bool stage_in = a.stage_in != 0;
+  int32_t *s_in = dyn;
+  int32_t *s_out = dyn + (stage_in ? TILE * i : 0);
   const uint64_t npairs = a.pair_end - a.pair_begin;
   const uint64_t ntiles = (npairs + TILE - 1) / TILE;
   const uint32_t G = gridDim.x, b = blockIdx.x;
@@ -367,77 +376,117 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
 
   for (uint64_t tile = lb; tile < ntiles; tile += G) {
     const uint64_t t0 = a.pair_begin + tile * TILE;
-    const uint64_t t1 = min(t0 + (uint64_t)TILE, a.pair_end);
-    if (tid == 0) {
-      uint64_t lo = 0, hi = a.n_rows;  // S[lo] <= t0 < S[hi]
+    const uint32_t len = (uint32_t)min((uint64_t)TILE, a.pair_end - t0);
+    if (wid == 0) {
+      // 64-way search by the first wave: S[lo] <= t0 < S[hi]; every round
+      // shrinks the interval 64-fold (5 dependent loads for 10^8 rows).
+      uint64_t lo = 0, hi = a.n_rows;
       while (hi - lo > 1) {
-        const uint64_t mid = (lo + hi) >> 1;
-        if (a.S[mid] <= t0)
+        const uint64_t step = (hi - lo + kWave - 1) / kWave;
+        const uint64_t idx = lo + (uint64_t)lane * step;
+        const bool le = idx < hi && a.S[idx] <= t0;  // true on lane 0
+        const uint64_t mask = wave_ballot(le);
+        const uint64_t k = 63 - __builtin_clzll(mask);
+        lo += k * step;
+        hi = min(hi, lo + step);
+      }
+      if (lane == 0) s_r0 = lo;
+    }
+    __syncthreads();
+    const uint64_t r0 = s_r0;
+    // window of row starts; row k intersects the tile iff sS[k] < len
+    for (int k = tid; k <= TILE; k += WG) {
+      const uint64_t r = r0 + k;
+      uint32_t rel;
+      if (k == 0) {
+        rel = 0;  // the first row may start before the tile: its lead is s_lead
+        s_lead = (uint32_t)(t0 - a.S[r0]);
+      } else {
+        const uint64_t v = (r <= a.n_rows) ? a.S[r] : ~0ull;
+        rel = (v - t0 > (uint64_t)TILE) ? (uint32_t)TILE + 1 : (uint32_t)(v - t0);
+      }
+      sS[k] = rel;
+    }
+    __syncthreads();
+    for (int k = tid; k < TILE; k += WG)
+      if (sS[k] < len && sS[k + 1] >= len) s_R = (uint32_t)k + 1;  // exactly one k
+    __syncthreads();
+    const uint32_t R = s_R, lead = s_lead;
+    if (stage_in) {
+      const int32_t *src = a.rows_in + r0 * (uint64_t)i;
+      for (uint32_t e = tid; e < R * (uint32_t)i; e += WG) s_in[e] = src[e];
+      __syncthreads();
+    }
+
+    // row of every item (search over the R rows of the tile)
+    uint32_t rk[ITEMS], off[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const uint32_t tl = (uint32_t)(it * WG + tid);
+      uint32_t lo = 0, hi = R;  // sS[lo] <= tl < sS[hi]
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sS[mid] <= tl)
           lo = mid;
         else
           hi = mid;
       }
-      s_r0 = lo;
+      rk[it] = lo;
+      off[it] = tl - sS[lo] + (lo == 0 ? lead : 0u);
     }
-    __syncthreads();
-    const uint64_t r0 = s_r0;
-    for (int k = tid; k <= TILE; k += WG) {
-      const uint64_t r = r0 + k;
-      sS[k] = (r <= a.n_rows) ? a.S[r] : ~0ull;
+    int64_t ab[ITEMS];
+    int ap[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      ab[it] = a.abase_in[r0 + rk[it]];
+      ap[it] = a.apos_in[r0 + rk[it]];
     }
-    __syncthreads();
+    int32_t wv[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const bool valid = (uint32_t)(it * WG + tid) < len;
+      wv[it] = a.g.gather[valid ? ab[it] + off[it] : ab[it]];
+    }
+    uint32_t cm[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) cm[it] = a.cmask[wv[it]];
 
     uint32_t keepbits = 0;
-    int32_t wv[ITEMS];
-    uint32_t rk[ITEMS];
     uint32_t nW[ITEMS];
     int64_t nbase[ITEMS];
     uint8_t napos[ITEMS];
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
-      wv[it] = 0;
-      rk[it] = 0;
       nW[it] = 0;
       nbase[it] = 0;
       napos[it] = 0;
-      const uint64_t t = t0 + (uint64_t)it * WG + tid;
-      if (t >= t1) continue;
-      int lo = 0, hi = TILE;  // sS[lo] <= t < sS[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (sS[mid] <= t)
-          lo = mid;
-        else
-          hi = mid;
-      }
-      const uint64_t r = r0 + lo;
-      const int32_t *row = a.rows_in + r * (uint64_t)i;
-      const int ap = a.apos_in[r];
-      const int32_t w = a.g.gather[a.abase_in[r] + (int64_t)(t - sS[lo])];
-      bool keep = (a.cmask[w] >> a.L.qbit) & 1;
-      uint32_t m = inj_mask;
-      while (keep && m) {
+      const bool valid = (uint32_t)(it * WG + tid) < len;
+      const int32_t w = wv[it];
+      const uint32_t k = rk[it];
+      bool keep = valid && ((cm[it] >> a.L.qbit) & 1);
+      for (uint32_t m = inj_mask; m; m &= m - 1) {
         const int j = __builtin_ctz(m);
-        m &= m - 1;
-        keep = row[j] != w;
+        const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
+        keep = keep && (x != w);
       }
-      m = a.L.nbr_mask & ~(1u << ap);
-      while (keep && m) {
+      for (uint32_t m = a.L.nbr_mask; m; m &= m - 1) {
         const int j = __builtin_ctz(m);
-        m &= m - 1;
-        keep = has_edge(a.g, row[j], w, probes);
+        if (keep && j != ap[it]) {
+          const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
+          keep = has_edge(a.g, x, w, probes);
+        }
       }
       if (MODE == kModeNext && keep) {
         // anchor of the next position: the earlier neighbour with the fewest
         // neighbours of the next label; an empty range ends the row here
-        uint32_t mm = a.L.next_nbr_mask, best = 0xffffffffu;
+        uint32_t best = 0xffffffffu;
         int bj = 0;
         int64_t bb = 0;
-        while (mm) {
+        for (uint32_t mm = a.L.next_nbr_mask; mm; mm &= mm - 1) {
           const int j = __builtin_ctz(mm);
-          mm &= mm - 1;
+          const int32_t x = (j == i) ? w : (stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j]);
           int64_t base;
-          const uint32_t d = label_range(a.g, j == i ? w : row[j], a.L.next_label, base);
+          const uint32_t d = label_range(a.g, x, a.L.next_label, base);
           if (d < best) {
             best = d;
             bj = j;
@@ -449,15 +498,12 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
         nbase[it] = bb;
         napos[it] = (uint8_t)bj;
       }
-      if (keep) {
-        keepbits |= 1u << it;
-        wv[it] = w;
-        rk[it] = (uint32_t)lo;
-      }
+      keepbits |= (uint32_t)keep << it;
     }
 
     if (MODE == kModeCount) {
       wg_count += __builtin_popcount(keepbits);
+      if (stage_in) __syncthreads();  // s_in is rewritten by the next tile
       continue;
     }
     // item-major compaction: survivors of item 0 of every lane, then item 1, ...
@@ -469,59 +515,62 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
       if (lane == 0) s_cnt[it * NW + wid] = (uint32_t)__popcll(mask);
     }
     __syncthreads();
-    if (tid == 0) {
-      uint64_t tot = 0;
-      for (int k = 0; k < ITEMS * NW; ++k) tot += s_cnt[k];
-      s_total = tot;
-      s_base = tot ? atomicAdd((unsigned long long *)a.counter, (unsigned long long)tot) : 0;
+    if (wid == 0) {
+      // exclusive scan of the ITEMS * NW counts (item-major), one lane each
+      const uint32_t c = lane < ITEMS * NW ? s_cnt[lane] : 0;
+      uint32_t inc = c;
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d, kWave);
+        if (lane >= d) inc += o;
+      }
+      if (lane < ITEMS * NW) s_cnt[lane] = inc - c;
+      const uint32_t tot = __shfl(inc, kWave - 1, kWave);
+      if (lane == 0) {
+        s_total = tot;
+        s_base = tot ? atomicAdd((unsigned long long *)a.counter, (unsigned long long)tot) : 0;
+      }
     }
     __syncthreads();
-    const uint64_t total = s_total, base = s_base;
-    if (total == 0) continue;
-    uint32_t before = 0;  // survivors ahead of this lane's item `it`
+    const uint32_t total = s_total;
+    const uint64_t base = s_base;
+    if (total == 0) {
+      if (stage_in) __syncthreads();
+      continue;
+    }
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
-      uint32_t pre = before;
-      for (int w2 = 0; w2 < wid; ++w2) pre += s_cnt[it * NW + w2];
-      for (int w2 = 0; w2 < NW; ++w2) before += s_cnt[it * NW + w2];
       if (!((keepbits >> it) & 1)) continue;
-      const uint32_t loc = pre + lofs[it];
+      const uint32_t loc = s_cnt[it * NW + wid] + lofs[it];
       const uint64_t pos = base + loc;
-      const int32_t *row = a.rows_in + (r0 + rk[it]) * (uint64_t)i;
+      const uint32_t k = rk[it];
       const int32_t w = wv[it];
       if (MODE == kModeNext) {
         a.W_out[pos] = nW[it];
         a.abase_out[pos] = nbase[it];
         a.apos_out[pos] = napos[it];
-        if (a.staged) {
-          int32_t *o = s_out + (uint64_t)loc * width;
-          for (int j = 0; j < i; ++j) o[j] = row[j];
-          o[i] = w;
-        } else {
-          int32_t *o = a.rows_out + pos * (uint64_t)width;
-          for (int j = 0; j < i; ++j) o[j] = row[j];
-          o[i] = w;
-        }
-      } else {  // kModeEmit: rows in query-id columns
-        if (a.staged) {
-          int32_t *o = s_out + (uint64_t)loc * width;
-          for (int j = 0; j < i; ++j) o[a.L.out_col[j]] = row[j];
-          o[a.L.out_col[i]] = w;
-        } else {
-          const uint64_t slot = pos - a.emit_base;
-          if (slot < a.emit_cap) {
-            int32_t *o = a.emit_rows + slot * (uint64_t)width;
-            for (int j = 0; j < i; ++j) o[a.L.out_col[j]] = row[j];
-            o[a.L.out_col[i]] = w;
-          }
-        }
       }
+      int32_t *o;
+      if (a.staged) {
+        o = s_out + loc * (uint32_t)width;
+      } else if (MODE == kModeNext) {
+        o = a.rows_out + pos * (uint64_t)width;
+      } else {
+        const uint64_t slot = pos - a.emit_base;
+        if (slot >= a.emit_cap) continue;
+        o = a.emit_rows + slot * (uint64_t)width;
+      }
+      for (int j = 0; j < i; ++j) {
+        const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
+        o[MODE == kModeNext ? j : a.L.out_col[j]] = x;
+      }
+      o[MODE == kModeNext ? i : a.L.out_col[i]] = w;
     }
     if (a.staged) {
       __syncthreads();
-      // contiguous copy of the tile's rows
+      // contiguous copy of the tile's rows, 16-byte stores where aligned
+      uint64_t nints = (uint64_t)total * width;
       int32_t *dst;
-      uint64_t nints = total * (uint64_t)width;
       if (MODE == kModeNext) {
         dst = a.rows_out + base * (uint64_t)width;
       } else {
@@ -530,9 +579,18 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
         if (room < total) nints = room * (uint64_t)width;
         dst = a.emit_rows + slot0 * (uint64_t)width;
       }
-      for (uint64_t k = tid; k < nints; k += WG) dst[k] = s_out[k];
-      __syncthreads();  // s_out is reused by the next tile
+      const uint32_t head = (uint32_t)min<uint64_t>(nints, (4 - (((uintptr_t)dst >> 2) & 3)) & 3);
+      if (tid < head) dst[tid] = s_out[tid];
+      const uint32_t nvec = (uint32_t)((nints - head) >> 2);
+      int4 *dv = reinterpret_cast<int4 *>(dst + head);
+      for (uint32_t v = tid; v < nvec; v += WG) {
+        const int32_t *sp = s_out + head + 4 * v;
+        dv[v] = make_int4(sp[0], sp[1], sp[2], sp[3]);
+      }
+      const uint32_t tail0 = head + 4 * nvec;
+      if (tail0 + tid < nints) dst[tail0 + tid] = s_out[tail0 + tid];
     }
+    __syncthreads();  // LDS buffers are rewritten by the next tile
   }
   if (MODE == kModeCount) {
     uint64_t total;
@@ -546,7 +604,7 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
   }
 }
 
-constexpr size_t kMaxStageBytes = 32 * 1024;
+constexpr size_t kMaxStageBytes = 48 * 1024;
 
 template <int WG, int ITEMS>
 void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
@@ -558,15 +616,20 @@ void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
   if (grid > kMaxGrid) grid = kMaxGrid;
   if (grid >= 8) grid &= ~7ull;
   const int width = (mode == kModeNext) ? a.L.i + 1 : a.L.q;
-  const size_t stage = TILE * (size_t)width * sizeof(int32_t);
-  a.staged = (mode != kModeCount && stage <= kMaxStageBytes) ? 1 : 0;
-  const size_t smem = a.staged ? stage : 0;
+  const size_t in_bytes = TILE * (size_t)a.L.i * sizeof(int32_t);
+  const size_t out_bytes = TILE * (size_t)width * sizeof(int32_t);
+  a.stage_in = (in_bytes <= kMaxStageBytes) ? 1 : 0;
+  a.staged = (a.stage_out_ok && mode != kModeCount &&
+              (a.stage_in ? in_bytes : 0) + out_bytes <= kMaxStageBytes)
+                 ? 1
+                 : 0;
+  const size_t smem = (a.stage_in ? in_bytes : 0) + (a.staged ? out_bytes : 0);
   switch (mode) {
     case kModeNext:
       hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeNext>), dim3((uint32_t)grid), dim3(WG), smem, s, a);
       break;
     case kModeCount:
-      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeCount>), dim3((uint32_t)grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeCount>), dim3((uint32_t)grid), dim3(WG), smem, s, a);
       break;
     default:
       hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeEmit>), dim3((uint32_t)grid), dim3(WG), smem, s, a);

@@ -3,6 +3,7 @@
 // inside a chunk), as in the verification loop of the paper's Alg. 1.
 #include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cstring>
 
 #include "gsm_internal.h"
@@ -29,6 +30,7 @@ struct Options {
   gsm_stats *stats = nullptr;
   int items = 4, wg = 256;
   bool profile = false;
+  int stage_out = 1;
 };
 
 Options read_opts(const gsm_match_opts *o, int q) {
@@ -50,6 +52,8 @@ Options read_opts(const gsm_match_opts *o, int q) {
   if (o->tile_items) r.items = o->tile_items;
   if (o->wg_size) r.wg = o->wg_size;
   r.profile = o->profile != 0;
+  if (o->struct_size >= offsetof(gsm_match_opts, flags) + sizeof(uint32_t))
+    r.stage_out = (o->flags & GSM_MATCH_NO_OUTPUT_STAGING) ? 0 : 1;
   if (r.rounds < 0 || r.rounds > 64) throw Error{GSM_E_INVALID_ARG, "filter_rounds out of [0, 64]"};
   if (r.root_q >= q) throw Error{GSM_E_INVALID_ARG, "root_qvertex >= q"};
   if (r.root_q >= 0 && r.root_mod == 0) throw Error{GSM_E_INVALID_ARG, "root_mod must be > 0"};
@@ -168,6 +172,7 @@ struct Matcher {
 
   void expand(ExpandArgs &a, int mode) {
     a.probes = dcnt + kCntProbes;
+    a.stage_out_ok = o.stage_out;
     if (o.profile) {
       auto pr = next_events();
       GSM_HIP(hipEventRecord(pr.first, s));
@@ -199,13 +204,20 @@ struct Matcher {
       staged_cap = std::min<uint64_t>(rest / shares / (uint64_t)(4 * p.q), uint64_t(1) << 26);
       if (staged_cap < 1) throw Error{GSM_E_BUDGET, "memory budget below one output row"};
     }
-    // give back buffers larger than this call's share
-    for (int i = 2; i < kMaxQ; ++i) {
-      if (ws.rows[i].bytes > std::max<uint64_t>(cap[i], 1) * 4 * i + 256) ws.rows[i].release();
-      if (ws.S[i].bytes > (std::max<uint64_t>(cap[i], 1) + 1) * 8 + 256) ws.S[i].release();
-      if (ws.W[i].bytes > std::max<uint64_t>(cap[i], 1) * 4 + 256) ws.W[i].release();
-      if (ws.apos[i].bytes > std::max<uint64_t>(cap[i], 1) + 256) ws.apos[i].release();
-      if (ws.abase[i].bytes > std::max<uint64_t>(cap[i], 1) * 8 + 256) ws.abase[i].release();
+    // Buffers are kept across calls (reallocation costs milliseconds); when
+    // what earlier calls left behind exceeds this call's budget, start over.
+    uint64_t held = ws.cmask.bytes + ws.cmask2.bytes + ws.emit.bytes;
+    for (int i = 0; i < kMaxQ; ++i)
+      held += ws.rows[i].bytes + ws.S[i].bytes + ws.W[i].bytes + ws.apos[i].bytes + ws.abase[i].bytes;
+    if (held > o.budget) {
+      for (int i = 2; i < kMaxQ; ++i) {
+        ws.rows[i].release();
+        ws.S[i].release();
+        ws.W[i].release();
+        ws.apos[i].release();
+        ws.abase[i].release();
+      }
+      ws.emit.release();
     }
   }
 
