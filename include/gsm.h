@@ -159,8 +159,8 @@ typedef struct gsm_match_opts {
   gsm_emit_fn emit;             /* optional row sink, called once per output chunk */
   void *emit_ctx;
   gsm_stats *stats;             /* optional */
-  int32_t tile_items;           /* pairs per thread per tile: 1, 2, 4, 8 (0 = auto) */
-  int32_t wg_size;              /* threads per workgroup: 128, 256, 512 (0 = auto) */
+  int32_t tile_items;           /* pairs per thread per tile: 1, 2, 4, 8 (0 = 4) */
+  int32_t wg_size;              /* threads per workgroup: 128, 256, 512 (0 = 512) */
   int32_t profile;              /* time each expansion launch with HIP events into stats */
   uint32_t flags;               /* GSM_MATCH_* tuning flags */
 } gsm_match_opts;

@@ -28,7 +28,7 @@ struct Options {
   gsm_emit_fn emit = nullptr;
   void *emit_ctx = nullptr;
   gsm_stats *stats = nullptr;
-  int items = 4, wg = 256;
+  int items = 4, wg = 512;
   bool profile = false;
   int stage_out = 1;
 };
