@@ -45,6 +45,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--items", type=int, default=0)
+    ap.add_argument("--workload", choices=["powerlaw", "batch"], default="powerlaw",
+                    help="powerlaw: embeddings/s (default); batch: batched vs per-launch queries/s")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (calibrates "
                          "the HBM byte counters of rocprofv3) and exit")
@@ -72,6 +75,9 @@ def main():
 
     from paper_2003_01527_amd import gsm
     from paper_2003_01527_amd import workloads as W
+
+    if args.workload == "batch":
+        return bench_batch(args)
 
     t = time.time()
     w = W.powerlaw()
@@ -179,6 +185,72 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """512 random-walk queries (3-8 vertices, edge density 0.3-1.0) on the 2^17
+    power-law graph, counted in batched launches vs one gsm_match per query."""
+    import numpy as np
+    import torch
+
+    from paper_2003_01527_amd import gsm
+    from paper_2003_01527_amd import workloads as W
+
+    from paper_2003_01527_amd import autotune
+
+    w = W.batch()
+    torch.cuda.init()
+    G = gsm.Graph.from_workload(w.graph)
+    Qs = [gsm.Query.from_workload(q) for q in w.queries]
+    budget = int(args.budget_gb * (1 << 30))
+    stream = torch.cuda.current_stream().cuda_stream
+    best = autotune.tune_batch(G, Qs, w.queries, budget, cache_path=args.tune_cache, log=log)
+    log("autotuned: %s" % best)
+    kw = dict(budget=budget, stream=stream, wg_size=best["wg_size"], tile_items=best["tile_items"])
+
+    def per_launch():
+        return np.array([gsm.match(G, Q, **kw)[0] for Q in Qs], dtype=np.uint64)
+
+    def batched():
+        return gsm.match_batch(G, Qs, batch_heavy_pairs=best["batch_heavy_pairs"], **kw)
+
+    ref = per_launch()
+    got = batched()
+    assert np.array_equal(ref, got), "batched counts differ from per-query counts"
+    res = {}
+    for name, fn in (("per_launch", per_launch), ("batched", batched)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t) / args.steps
+        log("%s: %.1f ms per pass of %d queries" % (name, res[name] * 1e3, len(Qs)))
+    qps_b = len(Qs) / res["batched"]
+    qps_p = len(Qs) / res["per_launch"]
+    out = {
+        "metric": "queries/s (batched)",
+        "value": round(qps_b, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["batched"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "batch: R-MAT 2^17 ef8, 16 Zipf labels; %d random-walk queries, 3-8 vertices, "
+                               "edge density 0.3-1.0; count only" % len(Qs),
+                   "embeddings_per_step": int(ref.sum())},
+        "per_launch_queries_per_s": round(qps_p, 1),
+        "autotuned": best,
+        "batched_over_per_launch": round(qps_b / qps_p, 3),
     }
     print(json.dumps(out), flush=True)
 

@@ -163,6 +163,9 @@ typedef struct gsm_match_opts {
   int32_t wg_size;              /* threads per workgroup: 128, 256, 512 (0 = 512) */
   int32_t profile;              /* time each expansion launch with HIP events into stats */
   uint32_t flags;               /* GSM_MATCH_* tuning flags */
+  uint64_t batch_heavy_pairs;   /* gsm_match_batch: a query whose first level has more
+                                   (row, neighbour) pairs runs on launches of its own
+                                   (0 = 2^18; UINT64_MAX = never) */
 } gsm_match_opts;
 
 /* Write output rows straight from registers instead of staging them in LDS. */
@@ -204,10 +207,14 @@ gsm_status gsm_match(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, 
 gsm_status gsm_match_min_budget(gsm_graph_t g, gsm_query_t qh, int32_t host_rows, uint64_t *bytes);
 
 /*
- * Counts the embeddings of nq queries on one graph in one pass of
- * level-synchronous batched launches (queries of different sizes and levels
- * share every launch; sizes stay on the device, so the whole pass is one
- * captured HIP graph).  counts[k] equals gsm_match's count for qs[k].
+ * Counts the embeddings of nq queries on one graph.  Queries whose first level
+ * is small share launches, grouped by size: their rows, tagged by query, form
+ * one frontier per level, so one first-frontier launch and, per level, one
+ * scan and one expansion launch serve a whole group (chunked by the budget
+ * like one query).
+ * Queries above opts->batch_heavy_pairs first-level pairs run on launches of
+ * their own, where a query-uniform kernel is faster.  counts[k] equals
+ * gsm_match's count for qs[k].  No root slice, rows or emit callback.
  */
 gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query_t *qs,
                            const gsm_match_opts *opts, uint64_t *counts);

@@ -1,0 +1,299 @@
+// Batched driver: many queries of one size share every launch.  Rows of all
+// of them live in one frontier per level, each tagged with its query; one
+// first-frontier launch, and per level one scan and one expansion launch serve
+// the whole group, chunked by the memory budget exactly like a single query.
+// The last level adds each completed embedding to its query's count.  Candidates are tested inline against
+// the graph's label, degree and neighbourhood encoding (the filter's first
+// round): per-query candidate arrays of n entries each would make every
+// candidate test of a large batch miss the caches, and refinement rounds are
+// a pruning choice that never changes a count.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+#include "gsm_internal.h"
+
+namespace gsm {
+
+namespace {
+
+constexpr int kCntRows = 0;
+constexpr int kCntPairs = 16;
+constexpr int kCntProbes = 33;
+
+struct BatchMatcher {
+  gsm_graph &g;
+  std::vector<const gsm_query *> qs;
+  Workspace &ws;
+  hipStream_t s;
+  int rounds, use_deg, use_ne, wg, items;
+  uint64_t budget;
+  int nq = 0, maxq = 0;
+  std::vector<Plan> plans;
+  DeviceGraph dg;
+  uint64_t cap[kMaxQ];
+  uint64_t *dcnt;
+  QueryArgs *d_qa = nullptr;
+  BatchLevel *d_bl = nullptr;
+  FirstBatch *d_fb = nullptr;
+  uint64_t *d_counts = nullptr;
+  uint64_t launches = 0;
+
+  BatchMatcher(gsm_graph &g_, const gsm_query *const *q_, int nq_, Workspace &ws_, hipStream_t s_)
+      : g(g_), qs(q_, q_ + nq_), ws(ws_), s(s_), nq(nq_) {
+    dg = DeviceGraph{g.rp,  g.col,  g.lab, g.deg, g.ne0, g.dne, g.col_lab ? g.col_lab : g.col,
+                     g.loff, g.loff_stride, g.n};
+    dcnt = ws.counters.as<uint64_t>();
+    for (auto *q : qs) {
+      plans.push_back(make_plan(g, *q));
+      maxq = std::max(maxq, q->q);
+    }
+  }
+
+  void sync() { GSM_HIP(hipStreamSynchronize(s)); }
+
+  void fetch_counters() {
+    GSM_HIP(hipMemcpyAsync(ws.h_counters, dcnt, 64 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    sync();
+  }
+
+  void upload_tables() {
+    std::vector<QueryArgs> qa(nq);
+    std::vector<BatchLevel> bl((size_t)nq * kMaxQ);
+    std::vector<FirstBatch> fb(nq);
+    for (int k = 0; k < nq; ++k) {
+      const Plan &p = plans[k];
+      QueryArgs &a = qa[k];
+      std::memset(&a, 0, sizeof(a));
+      a.q = p.q;
+      a.root_bit = -1;
+      a.root_mod = 1;
+      a.use_deg = use_deg;
+      a.use_ne = use_ne;
+      for (int u = 0; u < p.q; ++u) {
+        a.qlab[u] = p.qlab[u];
+        a.qdeg[u] = (uint32_t)p.qdeg[u];
+        a.qne[u] = p.qne[u];
+      }
+      for (int i = 0; i < p.q; ++i) {
+        BatchLevel &e = bl[(size_t)k * kMaxQ + i];
+        e.nbr_mask = p.backmask[i];
+        e.next_nbr_mask = (i + 1 < p.q) ? p.backmask[i + 1] : 0;
+        e.next_label = (i + 1 < p.q) ? p.qlab[p.order[i + 1]] : 0;
+        e.qbit = (uint16_t)p.order[i];
+        e.last = (i + 1 == p.q) ? 1 : 0;
+        const int u = p.order[i];
+        e.qlab = p.qlab[u];
+        e.qdeg = use_deg ? (uint32_t)p.qdeg[u] : 0;
+        e.qne = use_ne ? std::min<uint64_t>(p.qne[u], 0xffffffffull) : 0;
+      }
+      const int u0 = p.order[0];
+      fb[k].qlab0 = p.qlab[u0];
+      fb[k].qdeg0 = use_deg ? (uint32_t)p.qdeg[u0] : 0;
+      fb[k].qne0 = use_ne ? std::min<uint64_t>(p.qne[u0], 0xffffffffull) : 0;
+      fb[k].label1 = (p.q > 1) ? p.qlab[p.order[1]] : 0;
+      fb[k].single = (p.q == 1) ? 1 : 0;
+    }
+    const size_t b_qa = nq * sizeof(QueryArgs), b_bl = bl.size() * sizeof(BatchLevel),
+                 b_fb = nq * sizeof(FirstBatch);
+    const size_t o_bl = (b_qa + 255) & ~size_t(255), o_fb = (o_bl + b_bl + 255) & ~size_t(255);
+    ws.tables.reserve(o_fb + b_fb);
+    char *base = ws.tables.as<char>();
+    GSM_HIP(hipMemcpyAsync(base, qa.data(), b_qa, hipMemcpyHostToDevice, s));
+    GSM_HIP(hipMemcpyAsync(base + o_bl, bl.data(), b_bl, hipMemcpyHostToDevice, s));
+    GSM_HIP(hipMemcpyAsync(base + o_fb, fb.data(), b_fb, hipMemcpyHostToDevice, s));
+    d_qa = reinterpret_cast<QueryArgs *>(base);
+    d_bl = reinterpret_cast<BatchLevel *>(base + o_bl);
+    d_fb = reinterpret_cast<FirstBatch *>(base + o_fb);
+    ws.counts.reserve(std::max(nq, 1) * sizeof(uint64_t));
+    d_counts = ws.counts.as<uint64_t>();
+    GSM_HIP(hipMemsetAsync(d_counts, 0, std::max(nq, 1) * sizeof(uint64_t), s));
+  }
+
+  void plan_capacity() {
+    const uint64_t n = (uint64_t)std::max<int64_t>(g.n, 1);
+    uint64_t first = 0;
+    for (const Plan &p : plans) {
+      const int32_t l = p.qlab[p.order[0]];
+      first += (l >= 0 && (size_t)l < g.label_count.size()) ? (uint64_t)g.label_count[l] : 0;
+    }
+    first = std::max<uint64_t>(first, 1);
+    (void)n;
+    const uint64_t fixed = first * (4 + 2 + 4 + 8 + 1) + (first + 1) * 8 + 4096;
+    if (budget < fixed + 64) throw Error{GSM_E_BUDGET, "memory budget below the first frontiers"};
+    const uint64_t rest = budget - fixed;
+    const int shares = std::max(1, maxq - 2);
+    for (int i = 0; i < kMaxQ; ++i) cap[i] = 0;
+    cap[1] = first;
+    for (int i = 2; i < maxq; ++i) {
+      cap[i] = rest / shares / (uint64_t)(4 * i + 23);
+      if (cap[i] < 1) throw Error{GSM_E_BUDGET, "memory budget below one row of level " + std::to_string(i)};
+    }
+  }
+
+  void reserve_level(int i, uint64_t rows) {
+    ws.rows[i].reserve(rows * 4 * (uint64_t)i);
+    ws.qid[i].reserve(rows * 2);
+    ws.W[i].reserve(rows * 4);
+    ws.apos[i].reserve(rows);
+    ws.abase[i].reserve(rows * 8);
+    ws.S[i].reserve((rows + 1) * 8);
+  }
+
+  void process_level(int i) {
+    launch_scan(ws.W[i].as<uint32_t>(), dcnt + kCntRows + i, ws.S[i].as<uint64_t>(), dcnt + kCntPairs + i,
+                ws.scan_scratch.as<uint64_t>(), s);
+    fetch_counters();
+    const uint64_t N = ws.h_counters[kCntRows + i];
+    const uint64_t P = ws.h_counters[kCntPairs + i];
+    if (P == 0) return;
+    ExpandArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = dg;
+    a.cmask = nullptr;
+    a.rows_in = ws.rows[i].as<int32_t>();
+    a.apos_in = ws.apos[i].as<uint8_t>();
+    a.abase_in = ws.abase[i].as<int64_t>();
+    a.S = ws.S[i].as<uint64_t>();
+    a.n_rows = N;
+    a.L.i = i;
+    a.L.q = i + 1;
+    a.qid_in = ws.qid[i].as<uint16_t>();
+    a.blev = d_bl;
+    a.counts = d_counts;
+    a.probes = dcnt + kCntProbes;
+    a.stage_out_ok = 1;
+    const bool deepest = (i + 1 >= maxq);  // every query of the batch has maxq vertices
+    const uint64_t c = deepest ? P : cap[i + 1];
+    for (uint64_t b = 0; b < P; b += c) {
+      const uint64_t e = std::min(P, b + c);
+      if (!deepest) {
+        reserve_level(i + 1, e - b);
+        a.rows_out = ws.rows[i + 1].as<int32_t>();
+        a.W_out = ws.W[i + 1].as<uint32_t>();
+        a.apos_out = ws.apos[i + 1].as<uint8_t>();
+        a.abase_out = ws.abase[i + 1].as<int64_t>();
+        a.qid_out = ws.qid[i + 1].as<uint16_t>();
+      }
+      GSM_HIP(hipMemsetAsync(dcnt + kCntRows + i + 1, 0, sizeof(uint64_t), s));
+      a.counter = dcnt + kCntRows + i + 1;
+      a.pair_begin = b;
+      a.pair_end = e;
+      launch_expand(a, deepest ? kModeBatchLast : kModeBatch, wg, items, s);
+      ++launches;
+      if (!deepest) process_level(i + 1);
+    }
+  }
+
+  // First-level (row, neighbour) pairs of every query, from the first-frontier
+  // kernel in estimate mode (nothing is written but the totals).
+  std::vector<uint64_t> first_level_pairs() {
+    upload_tables();
+    GSM_HIP(hipMemsetAsync(d_counts, 0, std::max(nq, 1) * sizeof(uint64_t), s));
+    launch_compact_first_batch(dg, d_fb, nq, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, d_counts, s);
+    std::vector<uint64_t> out(nq);
+    GSM_HIP(hipMemcpyAsync(out.data(), d_counts, nq * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    sync();
+    return out;
+  }
+
+  void run(uint64_t *counts) {
+    upload_tables();
+    GSM_HIP(hipMemsetAsync(dcnt, 0, 64 * sizeof(uint64_t), s));
+    reserve_level(1, cap[1]);
+    launch_compact_first_batch(dg, d_fb, nq, ws.rows[1].as<int32_t>(),
+                               ws.qid[1].as<uint16_t>(), ws.W[1].as<uint32_t>(), ws.abase[1].as<int64_t>(),
+                               ws.apos[1].as<uint8_t>(), dcnt + kCntRows + 1, d_counts, nullptr, s);
+    if (maxq > 1) process_level(1);
+    GSM_HIP(hipMemcpyAsync(counts, d_counts, nq * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    sync();
+  }
+};
+
+}  // namespace
+
+}  // namespace gsm
+
+using gsm::Error;
+
+extern "C" gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query_t *qs,
+                                      const gsm_match_opts *opts, uint64_t *counts) {
+  try {
+    if (!g || nq < 0 || (nq > 0 && (!qs || !counts))) {
+      gsm::set_error("gsm_match_batch: invalid arguments");
+      return GSM_E_INVALID_ARG;
+    }
+    if (nq > 65535) {
+      gsm::set_error("gsm_match_batch: at most 65535 queries per batch");
+      return GSM_E_INVALID_ARG;
+    }
+    for (int k = 0; k < nq; ++k)
+      if (!qs[k]) {
+        gsm::set_error("gsm_match_batch: NULL query");
+        return GSM_E_INVALID_ARG;
+      }
+    if (nq == 0) return GSM_OK;
+    gsm_match_opts d;
+    gsm_match_opts_init(&d);
+    const gsm_match_opts &o = opts ? *opts : d;
+    if (o.root_qvertex >= 0 || o.rows_on_device || o.emit) {
+      gsm::set_error("gsm_match_batch counts only: no root slice, rows or emit callback");
+      return GSM_E_UNSUPPORTED;
+    }
+    if (o.filter_rounds < 0 || o.filter_rounds > 64) throw Error{GSM_E_INVALID_ARG, "filter_rounds out of [0, 64]"};
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (!g->ws) g->ws = new gsm::Workspace();
+    gsm::Workspace &ws = *g->ws;
+    const hipStream_t stream = (hipStream_t)o.hip_stream;
+    auto configure = [&](gsm::BatchMatcher &m) {
+      m.rounds = o.filter_rounds;
+      m.use_deg = o.use_degree;
+      m.use_ne = o.use_ne;
+      m.wg = o.wg_size ? o.wg_size : 512;
+      m.items = o.tile_items ? o.tile_items : 4;
+      m.budget = o.memory_budget_bytes ? o.memory_budget_bytes : (uint64_t(4) << 30);
+    };
+    // split: heavy queries on launches of their own, the rest shared
+    const uint64_t heavy_pairs = o.batch_heavy_pairs ? o.batch_heavy_pairs : (uint64_t(1) << 18);
+    std::vector<int> light;
+    std::vector<int> heavy;
+    {
+      gsm::BatchMatcher est(*g, qs, nq, ws, stream);
+      configure(est);
+      const std::vector<uint64_t> p1 = est.first_level_pairs();
+      for (int k = 0; k < nq; ++k) (qs[k]->q > 1 && p1[k] > heavy_pairs ? heavy : light).push_back(k);
+    }
+    uint64_t launches = 0;
+    for (int k : heavy) counts[k] = gsm::match_count_one(*g, *qs[k], o, ws);
+    // the shared launches group queries of one size, so every level of a group
+    // either writes the next frontier for all its rows or counts all of them
+    for (int qsize = 1; qsize <= gsm::kMaxQ; ++qsize) {
+      std::vector<int> grp;
+      for (int k : light)
+        if (qs[k]->q == qsize) grp.push_back(k);
+      if (grp.empty()) continue;
+      std::vector<const gsm_query *> sub;
+      for (int k : grp) sub.push_back(qs[k]);
+      std::vector<uint64_t> c(grp.size());
+      gsm::BatchMatcher m(*g, sub.data(), (int)sub.size(), ws, stream);
+      configure(m);
+      m.plan_capacity();
+      m.run(c.data());
+      launches += m.launches;
+      for (size_t j = 0; j < grp.size(); ++j) counts[grp[j]] = c[j];
+    }
+    if (o.stats) {
+      o.stats->expand_launches = launches;
+      o.stats->chunks[0] = heavy.size();
+      o.stats->chunks[1] = light.size();
+    }
+    return GSM_OK;
+  } catch (const Error &e) {
+    gsm::set_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc &) {
+    gsm::set_error("host allocation failed");
+    return GSM_E_OOM;
+  }
+}

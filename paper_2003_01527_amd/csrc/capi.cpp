@@ -215,6 +215,7 @@ gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *co
     GSM_HIP(hipMalloc((void **)&g->col, std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
     if (nnz) GSM_HIP(hipMemcpy(g->col, col, nnz * sizeof(int32_t), kind));
     GSM_HIP(hipMalloc((void **)&g->deg, std::max<int64_t>(n, 1) * sizeof(uint32_t)));
+    GSM_HIP(hipMalloc((void **)&g->dne, std::max<int64_t>(n, 1) * sizeof(uint2)));
     if (labels) {
       GSM_HIP(hipMalloc((void **)&g->lab, std::max<int64_t>(n, 1) * sizeof(int32_t)));
       if (n) GSM_HIP(hipMemcpy(g->lab, labels, n * sizeof(int32_t), kind));
@@ -259,6 +260,7 @@ void gsm_graph_destroy(gsm_graph_t g) {
   (void)hipFree(g->col);
   (void)hipFree(g->lab);
   (void)hipFree(g->deg);
+  (void)hipFree(g->dne);
   (void)hipFree(g->ne0);
   (void)hipFree(g->heavy);
   (void)hipFree(g->col_lab);

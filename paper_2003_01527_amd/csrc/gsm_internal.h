@@ -65,6 +65,7 @@ struct gsm_graph {
   int32_t *lab = nullptr;    // n, or null when unlabelled
   uint32_t *deg = nullptr;   // n
   uint64_t *ne0 = nullptr;   // n: sum over neighbours of (label+1); null when unlabelled
+  uint2 *dne = nullptr;      // n: (degree, NE saturated to 32 bits): one load per inline test
   int32_t *heavy = nullptr;  // vertices with degree > kHeavyDegree
   int64_t nheavy = 0;
   // label-grouped adjacency (labelled graphs with at most kMaxTableLabels labels):
@@ -138,6 +139,7 @@ struct DeviceGraph {
   const int32_t *lab;
   const uint32_t *deg;
   const uint64_t *ne0;
+  const uint2 *dne;        // (degree, NE saturated to 32 bits)
   const int32_t *gather;   // rows the expansion reads: col_lab when the table exists, else col
   const uint32_t *loff;    // label offsets per row, or null
   int32_t loff_stride;
@@ -162,7 +164,25 @@ size_t scan_scratch_elems();
 void launch_scan(const uint32_t *W, const uint64_t *n_dev, uint64_t *S, uint64_t *total_out,
                  uint64_t *scratch, hipStream_t s);
 
-enum ExpandMode { kModeNext = 0, kModeCount = 1, kModeEmit = 2 };
+// kModeBatch / kModeBatchLast: rows of many queries of one size, tagged by
+// query; kModeBatch writes the next level, kModeBatchLast (the queries' last
+// vertex) adds to per-query counts.
+enum ExpandMode { kModeNext = 0, kModeCount = 1, kModeEmit = 2, kModeBatch = 3, kModeBatchLast = 4 };
+
+// Per (query, level) parameters of a batched expansion.
+// The batched path tests candidates inline against the graph's per-vertex
+// label, degree and neighbourhood encoding (round 0 of the filter), so no
+// per-query candidate array is needed.
+struct BatchLevel {
+  uint32_t nbr_mask;       // positions j < i adjacent to position i
+  uint32_t next_nbr_mask;  // positions j <= i adjacent to position i+1
+  int32_t next_label;      // label of position i+1
+  uint16_t qbit;           // query id of position i
+  uint16_t last;           // position i is the query's last: count, do not write
+  uint64_t qne;            // NE of position i's query vertex (0 = no test)
+  uint32_t qdeg;           // degree of position i's query vertex (0 = no test)
+  int32_t qlab;            // label of position i's query vertex
+};
 
 struct ExpandArgs {
   DeviceGraph g;
@@ -185,6 +205,11 @@ struct ExpandArgs {
   int32_t *emit_rows;  // x q, query-id columns
   uint64_t emit_base;  // rows already emitted before this launch (for the cap)
   uint64_t emit_cap;
+  // kModeBatch: rows of many queries; row r belongs to query qid_in[r]
+  const uint16_t *qid_in;
+  uint16_t *qid_out;
+  const BatchLevel *blev;  // [nq * kMaxQ], entry (k, i)
+  uint64_t *counts;        // per-query embedding counts
   int32_t staged;        // output rows pass through LDS (dynamic shared memory)
   int32_t stage_in;      // the tile's input rows are copied to LDS
   int32_t stage_out_ok;  // the caller allows output staging
@@ -193,11 +218,36 @@ struct ExpandArgs {
 
 void launch_expand(const ExpandArgs &a, int mode, int wg, int items, hipStream_t s);
 
+// Batched filter and first frontier: query k's candidate mask is cmask + k*n.
+void launch_filter_init_batch(const DeviceGraph &g, const QueryArgs *qa_dev, int nq, uint16_t *cmask,
+                              hipStream_t s);
+void launch_filter_refine_batch(const DeviceGraph &g, const int32_t *heavy, int64_t nheavy,
+                                const QueryArgs *qa_dev, int nq, const uint16_t *prev, uint16_t *next,
+                                hipStream_t s);
+// First frontier of every query: rows tagged with the query id; queries with a
+// single vertex are counted into counts[k] directly.
+struct FirstBatch {
+  uint64_t qne0;      // position 0: NE (0 = no test)
+  uint32_t qdeg0;     // position 0: degree (0 = no test)
+  int32_t qlab0;      // position 0: label
+  int32_t label1;     // label of position 1 (unused when q == 1)
+  int32_t single;     // q == 1
+};
+void launch_compact_first_batch(const DeviceGraph &g, const FirstBatch *fb_dev,
+                                int nq, int32_t *rows, uint16_t *qid, uint32_t *W, int64_t *abase,
+                                uint8_t *apos, uint64_t *counter, uint64_t *counts, uint64_t *pairs1,
+                                hipStream_t s);
+// Count-only match of one query on the workspace (the single-query driver).
+uint64_t match_count_one(gsm_graph &g, const gsm_query &q, const gsm_match_opts &o, Workspace &ws);
+
 // -------------------------------------------------------------- workspace --
 
 struct Workspace {
   DevBuf cmask, cmask2;
   DevBuf rows[kMaxQ], W[kMaxQ], apos[kMaxQ], abase[kMaxQ], S[kMaxQ];
+  DevBuf qid[kMaxQ];  // batched rows: query of each row
+  DevBuf tables;      // batched per-query parameter tables
+  DevBuf counts;      // batched per-query counts
   DevBuf counters;  // kMaxQ + 8 uint64
   DevBuf scan_scratch;
   DevBuf emit;      // staging for host-bound rows

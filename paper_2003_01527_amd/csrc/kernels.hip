@@ -4,6 +4,8 @@
 // nothing is a dense contraction, so no kernel uses the matrix cores.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "gsm_internal.h"
 
 namespace gsm {
@@ -81,7 +83,7 @@ __device__ __forceinline__ bool has_edge(const DeviceGraph &g, int32_t x, int32_
 
 // deg[v] and NE0[v] = sum over neighbours of (label+1); 16 lanes per vertex.
 __global__ void k_graph_stats(const int64_t *rp, const int32_t *col, const int32_t *lab,
-                              int64_t n, uint32_t *deg, uint64_t *ne0) {
+                              int64_t n, uint32_t *deg, uint64_t *ne0, uint2 *dne) {
   constexpr int G = 16;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -96,6 +98,8 @@ __global__ void k_graph_stats(const int64_t *rp, const int32_t *col, const int32
     if (sub == 0) {
       deg[v] = (uint32_t)(e - b);
       if (ne0) ne0[v] = s;
+      const uint64_t ne = lab ? s : (uint64_t)(e - b);
+      dne[v] = make_uint2((uint32_t)(e - b), ne > 0xffffffffull ? 0xffffffffu : (uint32_t)ne);
     }
   }
 }
@@ -257,6 +261,159 @@ __global__ __launch_bounds__(256) void k_compact_first(DeviceGraph g, const uint
   }
 }
 
+// ---------------------------------------------------- batched filter --
+
+__global__ void k_filter_init_batch(DeviceGraph g, const QueryArgs *qa_all, uint16_t *cmask) {
+  __shared__ QueryArgs qa;
+  if (threadIdx.x == 0) qa = qa_all[blockIdx.y];
+  __syncthreads();
+  uint16_t *cm = cmask + (int64_t)blockIdx.y * g.n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
+    const int32_t lv = g.lab ? g.lab[v] : 0;
+    const uint32_t d = g.deg[v];
+    const uint64_t ne = g.ne0 ? g.ne0[v] : (uint64_t)d;
+    cm[v] = candidate_bits(qa, lv, d, ne, (uint64_t)v);
+  }
+}
+
+__global__ void k_refine_light_batch(DeviceGraph g, const QueryArgs *qa_all, const uint16_t *prev_all,
+                                     uint16_t *next_all) {
+  __shared__ QueryArgs qa;
+  if (threadIdx.x == 0) qa = qa_all[blockIdx.y];
+  __syncthreads();
+  const uint16_t *prev = prev_all + (int64_t)blockIdx.y * g.n;
+  uint16_t *next = next_all + (int64_t)blockIdx.y * g.n;
+  constexpr int G = 16;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sub = threadIdx.x & (G - 1);
+  for (int64_t v = gid / G; v < g.n; v += nthreads / G) {
+    const uint16_t pm = prev[v];
+    const int64_t b = g.rp[v], e = g.rp[v + 1];
+    if (e - b > kHeavyDegree) continue;
+    if (pm == 0) {
+      if (sub == 0) next[v] = 0;
+      continue;
+    }
+    uint32_t c = 0;
+    uint64_t s = 0;
+    for (int64_t k = b + sub; k < e; k += G) {
+      const int32_t w = g.col[k];
+      if (prev[w]) {
+        c += 1;
+        s += g.lab ? (uint64_t)g.lab[w] + 1 : 1;
+      }
+    }
+#pragma unroll
+    for (int d = G / 2; d > 0; d >>= 1) {
+      c += __shfl_xor(c, d, G);
+      s += __shfl_xor(s, d, G);
+    }
+    if (sub == 0) next[v] = refine_bits(qa, pm, c, s);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_refine_heavy_batch(DeviceGraph g, const QueryArgs *qa_all,
+                                                            const int32_t *heavy, int64_t nheavy,
+                                                            const uint16_t *prev_all,
+                                                            uint16_t *next_all) {
+  __shared__ QueryArgs qa;
+  __shared__ uint64_t sw[256 / kWave];
+  if (threadIdx.x == 0) qa = qa_all[blockIdx.y];
+  __syncthreads();
+  const uint16_t *prev = prev_all + (int64_t)blockIdx.y * g.n;
+  uint16_t *next = next_all + (int64_t)blockIdx.y * g.n;
+  for (int64_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
+    const int32_t v = heavy[h];
+    const uint16_t pm = prev[v];
+    if (pm == 0) {
+      if (threadIdx.x == 0) next[v] = 0;
+      continue;
+    }
+    const int64_t b = g.rp[v], e = g.rp[v + 1];
+    uint64_t c = 0, s = 0;
+    for (int64_t k = b + threadIdx.x; k < e; k += blockDim.x) {
+      const int32_t w = g.col[k];
+      if (prev[w]) {
+        c += 1;
+        s += g.lab ? (uint64_t)g.lab[w] + 1 : 1;
+      }
+    }
+    uint64_t tc, ts;
+    block_excl_scan<256>(c, sw, &tc);
+    block_excl_scan<256>(s, sw, &ts);
+    if (threadIdx.x == 0) next[v] = refine_bits(qa, pm, (uint32_t)tc, ts);
+  }
+}
+
+// Round-0 candidate test without a per-query array: one 8-byte load of
+// (degree, NE) and, where neighbours were not gathered by label, the label.
+// NE is stored saturated at 2^32-1 and the host clamps the query's NE to the
+// same value, so the test can only accept more vertices than the exact one
+// (it stays sound; every embedding is still verified edge by edge).
+__device__ __forceinline__ bool inline_candidate(const DeviceGraph &g, int32_t v, int32_t qlab,
+                                                 uint32_t qdeg, uint64_t qne, bool label_known) {
+  const uint2 dn = g.dne[v];
+  bool ok = dn.x >= qdeg && (uint64_t)dn.y >= qne;
+  if (!label_known) ok = ok && (g.lab ? g.lab[v] == qlab : qlab == 0);
+  return ok;
+}
+
+// rows == null: estimate only, adding each query's first-level pair total
+// (the sum of its rows' range sizes) to pairs1[k] and writing nothing else.
+__global__ __launch_bounds__(256) void k_compact_first_batch(DeviceGraph g, const FirstBatch *fb_all,
+                                                             int32_t *rows,
+                                                             uint16_t *qid, uint32_t *W, int64_t *abase,
+                                                             uint8_t *apos, uint64_t *counter,
+                                                             uint64_t *counts, uint64_t *pairs1) {
+  const int k = blockIdx.y;
+  const FirstBatch fb = fb_all[k];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  uint32_t single = 0;
+  for (int64_t vb = start - lane; vb < g.n; vb += stride) {
+    const int64_t v = vb + lane;
+    bool keep = false;
+    uint32_t d = 0;
+    int64_t b = 0;
+    if (v < g.n) {
+      keep = inline_candidate(g, (int32_t)v, fb.qlab0, fb.qdeg0, fb.qne0, false);
+      if (keep && !fb.single) {
+        d = label_range(g, (int32_t)v, fb.label1, b);
+        keep = d > 0;
+      }
+    }
+    const uint64_t mask = wave_ballot(keep);
+    if (mask == 0) continue;
+    if (fb.single) {
+      single += (uint32_t)__popcll(mask);
+      continue;
+    }
+    if (!rows) {
+      uint64_t sum = keep ? d : 0;
+#pragma unroll
+      for (int o = kWave / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, kWave);
+      if (lane == 0) atomicAdd((unsigned long long *)(pairs1 + k), (unsigned long long)sum);
+      continue;
+    }
+    uint64_t base = 0;
+    if (lane == 0) base = atomicAdd((unsigned long long *)counter, (unsigned long long)__popcll(mask));
+    base = __shfl(base, 0, kWave);
+    if (keep) {
+      const uint64_t pos = base + lane_prefix(mask);
+      rows[pos] = (int32_t)v;
+      qid[pos] = (uint16_t)k;
+      W[pos] = d;
+      abase[pos] = b;
+      apos[pos] = 0;
+    }
+  }
+  if (fb.single && lane == 0 && single && counts)
+    atomicAdd((unsigned long long *)(counts + k), (unsigned long long)single);
+}
+
 // ------------------------------------------------------------------ scan --
 
 constexpr int kScanBlocks = 512;
@@ -349,6 +506,7 @@ __global__ __launch_bounds__(kScanWG) void k_scan_down(const uint32_t *W, const 
 // they fit.
 template <int WG, int ITEMS, int MODE>
 __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
+  constexpr bool BATCHED = (MODE == kModeBatch || MODE == kModeBatchLast);
   constexpr int TILE = WG * ITEMS;
   constexpr int NW = WG / kWave;
   __shared__ uint32_t sS[TILE + 1];  // row starts relative to the tile, clamped to TILE+1
@@ -360,7 +518,7 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int i = a.L.i;
-  const int width = (MODE == kModeNext) ? i + 1 : a.L.q;
+  const int width = (MODE == kModeNext || MODE == kModeBatch) ? i + 1 : a.L.q;
   const bool stage_in = a.stage_in != 0;
   int32_t *s_in = dyn;
   int32_t *s_out = dyn + (stage_in ? TILE * i : 0);
@@ -373,6 +531,8 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
   const uint32_t inj_mask = ((1u << i) - 1u) & ~a.L.nbr_mask;
   uint64_t wg_count = 0;
   uint32_t probes = 0;
+  uint32_t acc_k = 0xffffffffu;  // kModeBatch: this wave's pending (query, count)
+  uint64_t acc_c = 0;
 
   for (uint64_t tile = lb; tile < ntiles; tile += G) {
     const uint64_t t0 = a.pair_begin + tile * TILE;
@@ -415,10 +575,10 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
     if (stage_in) {
       const int32_t *src = a.rows_in + r0 * (uint64_t)i;
       for (uint32_t e = tid; e < R * (uint32_t)i; e += WG) s_in[e] = src[e];
-      __syncthreads();
     }
+    if (stage_in) __syncthreads();
 
-    // row of every item (search over the R rows of the tile)
+    // ---- evaluation (no barriers): row, candidate, checks of every item
     uint32_t rk[ITEMS], off[ITEMS];
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
@@ -436,10 +596,12 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
     }
     int64_t ab[ITEMS];
     int ap[ITEMS];
+    uint32_t qk[ITEMS];
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
       ab[it] = a.abase_in[r0 + rk[it]];
       ap[it] = a.apos_in[r0 + rk[it]];
+      qk[it] = BATCHED ? a.qid_in[r0 + rk[it]] : 0u;
     }
     int32_t wv[ITEMS];
 #pragma unroll
@@ -447,148 +609,231 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
       const bool valid = (uint32_t)(it * WG + tid) < len;
       wv[it] = a.g.gather[valid ? ab[it] + off[it] : ab[it]];
     }
-    uint32_t cm[ITEMS];
+    // kModeBatch: a wave whose items all belong to one query reads that
+    // query's level entry once, into scalar registers
+    bool wuni = true;
+    uint32_t q0 = 0;
+    if (BATCHED) {
+      q0 = __builtin_amdgcn_readfirstlane(qk[0]);
+      bool same = true;
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) cm[it] = a.cmask[wv[it]];
+      for (int it = 0; it < ITEMS; ++it) same = same && qk[it] == q0;
+      wuni = wave_ballot(!same) == 0;
+    }
 
-    uint32_t keepbits = 0;
+    uint32_t keepbits = 0, cntbits = 0;
     uint32_t nW[ITEMS];
     int64_t nbase[ITEMS];
     uint8_t napos[ITEMS];
+    auto evaluate = [&](auto uni_tag) {
+      constexpr bool UNI = decltype(uni_tag)::value;
+      BatchLevel ubl{};
+      if (BATCHED && UNI) ubl = a.blev[q0 * kMaxQ + i];  // uniform address: scalar loads
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      nW[it] = 0;
-      nbase[it] = 0;
-      napos[it] = 0;
-      const bool valid = (uint32_t)(it * WG + tid) < len;
-      const int32_t w = wv[it];
-      const uint32_t k = rk[it];
-      bool keep = valid && ((cm[it] >> a.L.qbit) & 1);
-      for (uint32_t m = inj_mask; m; m &= m - 1) {
-        const int j = __builtin_ctz(m);
-        const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
-        keep = keep && (x != w);
-      }
-      for (uint32_t m = a.L.nbr_mask; m; m &= m - 1) {
-        const int j = __builtin_ctz(m);
-        if (keep && j != ap[it]) {
-          const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
-          keep = has_edge(a.g, x, w, probes);
+      for (int it = 0; it < ITEMS; ++it) {
+        uint32_t p_nbr, p_next_nbr, p_qbit, p_last;
+        int32_t p_next_label;
+        bool cand;
+        if (BATCHED) {
+          const BatchLevel bl = UNI ? ubl : a.blev[qk[it] * kMaxQ + i];
+          p_nbr = bl.nbr_mask;
+          p_next_nbr = bl.next_nbr_mask;
+          p_next_label = bl.next_label;
+          p_qbit = bl.qbit;
+          p_last = (MODE == kModeBatchLast);
+          cand = inline_candidate(a.g, wv[it], bl.qlab, bl.qdeg, bl.qne, a.g.loff != nullptr);
+        } else {
+          p_nbr = a.L.nbr_mask;
+          p_next_nbr = a.L.next_nbr_mask;
+          p_next_label = a.L.next_label;
+          p_qbit = a.L.qbit;
+          p_last = (MODE != kModeNext);
+          cand = (a.cmask[wv[it]] >> p_qbit) & 1;
         }
-      }
-      if (MODE == kModeNext && keep) {
-        // anchor of the next position: the earlier neighbour with the fewest
-        // neighbours of the next label; an empty range ends the row here
-        uint32_t best = 0xffffffffu;
-        int bj = 0;
-        int64_t bb = 0;
-        for (uint32_t mm = a.L.next_nbr_mask; mm; mm &= mm - 1) {
-          const int j = __builtin_ctz(mm);
-          const int32_t x = (j == i) ? w : (stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j]);
-          int64_t base;
-          const uint32_t d = label_range(a.g, x, a.L.next_label, base);
-          if (d < best) {
-            best = d;
-            bj = j;
-            bb = base;
+        nW[it] = 0;
+        nbase[it] = 0;
+        napos[it] = 0;
+        const bool valid = (uint32_t)(it * WG + tid) < len;
+        const int32_t w = wv[it];
+        const uint32_t k = rk[it];
+        bool keep = valid && cand;
+        const uint32_t inj = ((1u << i) - 1u) & ~p_nbr;
+        for (uint32_t m = inj; m; m &= m - 1) {
+          const int j = __builtin_ctz(m);
+          const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
+          keep = keep && (x != w);
+        }
+        for (uint32_t m = p_nbr; m; m &= m - 1) {
+          const int j = __builtin_ctz(m);
+          if (keep && j != ap[it]) {
+            const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
+            keep = has_edge(a.g, x, w, probes);
           }
         }
-        keep = best > 0;
-        nW[it] = best;
-        nbase[it] = bb;
-        napos[it] = (uint8_t)bj;
+        if ((MODE == kModeNext || MODE == kModeBatch) && keep && !p_last) {
+          // anchor of the next position: the earlier neighbour with the fewest
+          // neighbours of the next label; an empty range ends the row here
+          uint32_t best = 0xffffffffu;
+          int bj = 0;
+          int64_t bb = 0;
+          for (uint32_t mm = p_next_nbr; mm; mm &= mm - 1) {
+            const int j = __builtin_ctz(mm);
+            const int32_t x = (j == i) ? w : (stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j]);
+            int64_t base;
+            const uint32_t d = label_range(a.g, x, p_next_label, base);
+            if (d < best) {
+              best = d;
+              bj = j;
+              bb = base;
+            }
+          }
+          keep = best > 0;
+          nW[it] = best;
+          nbase[it] = bb;
+          napos[it] = (uint8_t)bj;
+        }
+        if (MODE == kModeBatchLast)
+          cntbits |= (uint32_t)keep << it;
+        else
+          keepbits |= (uint32_t)keep << it;
       }
-      keepbits |= (uint32_t)keep << it;
-    }
+    };
+    if (BATCHED && !wuni)
+      evaluate(std::false_type{});
+    else
+      evaluate(std::true_type{});
 
     if (MODE == kModeCount) {
       wg_count += __builtin_popcount(keepbits);
-      if (stage_in) __syncthreads();  // s_in is rewritten by the next tile
-      continue;
-    }
-    // item-major compaction: survivors of item 0 of every lane, then item 1, ...
-    uint32_t lofs[ITEMS];
+    } else if (MODE == kModeBatchLast) {
+      {
+        // embeddings completed here go to their query's count; each wave keeps
+        // a running (query, count) pair, flushed with one atomic when the
+        // query changes (acc_k and acc_c are the same on every lane)
+        if (wuni) {
+          uint64_t c = 0;
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      const uint64_t mask = wave_ballot((keepbits >> it) & 1);
-      lofs[it] = lane_prefix(mask);
-      if (lane == 0) s_cnt[it * NW + wid] = (uint32_t)__popcll(mask);
-    }
-    __syncthreads();
-    if (wid == 0) {
-      // exclusive scan of the ITEMS * NW counts (item-major), one lane each
-      const uint32_t c = lane < ITEMS * NW ? s_cnt[lane] : 0;
-      uint32_t inc = c;
+          for (int it = 0; it < ITEMS; ++it) c += (uint64_t)__popcll(wave_ballot((cntbits >> it) & 1));
+          if (c) {
+            if (q0 != acc_k) {
+              if (lane == 0 && acc_c)
+                atomicAdd((unsigned long long *)(a.counts + acc_k), (unsigned long long)acc_c);
+              acc_k = q0;
+              acc_c = 0;
+            }
+            acc_c += c;
+          }
+        } else {
 #pragma unroll
-      for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t o = __shfl_up(inc, d, kWave);
-        if (lane >= d) inc += o;
+          for (int it = 0; it < ITEMS; ++it) {
+            bool pend = (cntbits >> it) & 1;
+            uint64_t act = wave_ballot(pend);
+            while (act) {
+              const int leader = __builtin_ctzll(act);
+              const uint32_t lk = __shfl(qk[it], leader, kWave);
+              const bool mine = pend && qk[it] == lk;
+              const uint64_t same = wave_ballot(mine);
+              if (lk != acc_k) {
+                if (lane == 0 && acc_c)
+                  atomicAdd((unsigned long long *)(a.counts + acc_k), (unsigned long long)acc_c);
+                acc_k = lk;
+                acc_c = 0;
+              }
+              acc_c += (uint64_t)__popcll(same);
+              if (mine) pend = false;
+              act = wave_ballot(pend);
+            }
+          }
+        }
       }
-      if (lane < ITEMS * NW) s_cnt[lane] = inc - c;
-      const uint32_t tot = __shfl(inc, kWave - 1, kWave);
-      if (lane == 0) {
-        s_total = tot;
-        s_base = tot ? atomicAdd((unsigned long long *)a.counter, (unsigned long long)tot) : 0;
-      }
-    }
-    __syncthreads();
-    const uint32_t total = s_total;
-    const uint64_t base = s_base;
-    if (total == 0) {
-      if (stage_in) __syncthreads();
-      continue;
-    }
+    } else {
+      // ---- compaction and writes (workgroup barriers)
+      {
+        // item-major compaction: survivors of item 0 of every lane, then item 1, ...
+        uint32_t lofs[ITEMS];
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      if (!((keepbits >> it) & 1)) continue;
-      const uint32_t loc = s_cnt[it * NW + wid] + lofs[it];
-      const uint64_t pos = base + loc;
-      const uint32_t k = rk[it];
-      const int32_t w = wv[it];
-      if (MODE == kModeNext) {
-        a.W_out[pos] = nW[it];
-        a.abase_out[pos] = nbase[it];
-        a.apos_out[pos] = napos[it];
+        for (int it = 0; it < ITEMS; ++it) {
+          const uint64_t mask = wave_ballot((keepbits >> it) & 1);
+          lofs[it] = lane_prefix(mask);
+          if (lane == 0) s_cnt[it * NW + wid] = (uint32_t)__popcll(mask);
+        }
+        __syncthreads();
+        if (wid == 0) {
+          // exclusive scan of the ITEMS * NW counts (item-major), one lane each
+          const uint32_t c = lane < ITEMS * NW ? s_cnt[lane] : 0;
+          uint32_t inc = c;
+#pragma unroll
+          for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o = __shfl_up(inc, d, kWave);
+            if (lane >= d) inc += o;
+          }
+          if (lane < ITEMS * NW) s_cnt[lane] = inc - c;
+          const uint32_t tot = __shfl(inc, kWave - 1, kWave);
+          if (lane == 0) {
+            s_total = tot;
+            s_base = tot ? atomicAdd((unsigned long long *)a.counter, (unsigned long long)tot) : 0;
+          }
+        }
+        __syncthreads();
+        const uint32_t total = s_total;
+        const uint64_t base = s_base;
+        if (total > 0) {
+          constexpr bool kIdOrder = (MODE == kModeNext || MODE == kModeBatch);
+#pragma unroll
+          for (int it = 0; it < ITEMS; ++it) {
+            if (!((keepbits >> it) & 1)) continue;
+            const uint32_t loc = s_cnt[it * NW + wid] + lofs[it];
+            const uint64_t pos = base + loc;
+            const uint32_t k = rk[it];
+            const int32_t w = wv[it];
+            if (kIdOrder) {
+              a.W_out[pos] = nW[it];
+              a.abase_out[pos] = nbase[it];
+              a.apos_out[pos] = napos[it];
+              if (MODE == kModeBatch) a.qid_out[pos] = (uint16_t)qk[it];
+            }
+            int32_t *o;
+            if (a.staged) {
+              o = s_out + loc * (uint32_t)width;
+            } else if (kIdOrder) {
+              o = a.rows_out + pos * (uint64_t)width;
+            } else {
+              const uint64_t slot = pos - a.emit_base;
+              if (slot >= a.emit_cap) continue;
+              o = a.emit_rows + slot * (uint64_t)width;
+            }
+            for (int j = 0; j < i; ++j) {
+              const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
+              o[kIdOrder ? j : a.L.out_col[j]] = x;
+            }
+            o[kIdOrder ? i : a.L.out_col[i]] = w;
+          }
+          if (a.staged) {
+            __syncthreads();
+            // contiguous copy of the tile's rows, 16-byte stores where aligned
+            uint64_t nints = (uint64_t)total * width;
+            int32_t *dst;
+            if (kIdOrder) {
+              dst = a.rows_out + base * (uint64_t)width;
+            } else {
+              const uint64_t slot0 = base - a.emit_base;
+              const uint64_t room = slot0 < a.emit_cap ? a.emit_cap - slot0 : 0;
+              if (room < total) nints = room * (uint64_t)width;
+              dst = a.emit_rows + slot0 * (uint64_t)width;
+            }
+            const uint32_t head = (uint32_t)min<uint64_t>(nints, (4 - (((uintptr_t)dst >> 2) & 3)) & 3);
+            if (tid < head) dst[tid] = s_out[tid];
+            const uint32_t nvec = (uint32_t)((nints - head) >> 2);
+            int4 *dv = reinterpret_cast<int4 *>(dst + head);
+            for (uint32_t v = tid; v < nvec; v += WG) {
+              const int32_t *sp = s_out + head + 4 * v;
+              dv[v] = make_int4(sp[0], sp[1], sp[2], sp[3]);
+            }
+            const uint32_t tail0 = head + 4 * nvec;
+            if (tail0 + tid < nints) dst[tail0 + tid] = s_out[tail0 + tid];
+          }
+        }
       }
-      int32_t *o;
-      if (a.staged) {
-        o = s_out + loc * (uint32_t)width;
-      } else if (MODE == kModeNext) {
-        o = a.rows_out + pos * (uint64_t)width;
-      } else {
-        const uint64_t slot = pos - a.emit_base;
-        if (slot >= a.emit_cap) continue;
-        o = a.emit_rows + slot * (uint64_t)width;
-      }
-      for (int j = 0; j < i; ++j) {
-        const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
-        o[MODE == kModeNext ? j : a.L.out_col[j]] = x;
-      }
-      o[MODE == kModeNext ? i : a.L.out_col[i]] = w;
-    }
-    if (a.staged) {
-      __syncthreads();
-      // contiguous copy of the tile's rows, 16-byte stores where aligned
-      uint64_t nints = (uint64_t)total * width;
-      int32_t *dst;
-      if (MODE == kModeNext) {
-        dst = a.rows_out + base * (uint64_t)width;
-      } else {
-        const uint64_t slot0 = base - a.emit_base;
-        const uint64_t room = slot0 < a.emit_cap ? a.emit_cap - slot0 : 0;
-        if (room < total) nints = room * (uint64_t)width;
-        dst = a.emit_rows + slot0 * (uint64_t)width;
-      }
-      const uint32_t head = (uint32_t)min<uint64_t>(nints, (4 - (((uintptr_t)dst >> 2) & 3)) & 3);
-      if (tid < head) dst[tid] = s_out[tid];
-      const uint32_t nvec = (uint32_t)((nints - head) >> 2);
-      int4 *dv = reinterpret_cast<int4 *>(dst + head);
-      for (uint32_t v = tid; v < nvec; v += WG) {
-        const int32_t *sp = s_out + head + 4 * v;
-        dv[v] = make_int4(sp[0], sp[1], sp[2], sp[3]);
-      }
-      const uint32_t tail0 = head + 4 * nvec;
-      if (tail0 + tid < nints) dst[tail0 + tid] = s_out[tail0 + tid];
     }
     __syncthreads();  // LDS buffers are rewritten by the next tile
   }
@@ -597,6 +842,8 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
     block_excl_scan<WG>(wg_count, sw, &total);
     if (tid == 0 && total) atomicAdd((unsigned long long *)a.counter, (unsigned long long)total);
   }
+  if (MODE == kModeBatchLast && lane == 0 && acc_c)
+    atomicAdd((unsigned long long *)(a.counts + acc_k), (unsigned long long)acc_c);
   if (a.probes) {
     uint64_t total;
     block_excl_scan<WG>(probes, sw, &total);
@@ -615,11 +862,11 @@ void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
   const uint64_t kMaxGrid = 1u << 20;
   if (grid > kMaxGrid) grid = kMaxGrid;
   if (grid >= 8) grid &= ~7ull;
-  const int width = (mode == kModeNext) ? a.L.i + 1 : a.L.q;
+  const int width = (mode == kModeNext || mode == kModeBatch) ? a.L.i + 1 : a.L.q;
   const size_t in_bytes = TILE * (size_t)a.L.i * sizeof(int32_t);
   const size_t out_bytes = TILE * (size_t)width * sizeof(int32_t);
   a.stage_in = (in_bytes <= kMaxStageBytes) ? 1 : 0;
-  a.staged = (a.stage_out_ok && mode != kModeCount &&
+  a.staged = (a.stage_out_ok && mode != kModeCount && mode != kModeBatchLast &&
               (a.stage_in ? in_bytes : 0) + out_bytes <= kMaxStageBytes)
                  ? 1
                  : 0;
@@ -630,6 +877,12 @@ void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
       break;
     case kModeCount:
       hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeCount>), dim3((uint32_t)grid), dim3(WG), smem, s, a);
+      break;
+    case kModeBatch:
+      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeBatch>), dim3((uint32_t)grid), dim3(WG), smem, s, a);
+      break;
+    case kModeBatchLast:
+      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeBatchLast>), dim3((uint32_t)grid), dim3(WG), smem, s, a);
       break;
     default:
       hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeEmit>), dim3((uint32_t)grid), dim3(WG), smem, s, a);
@@ -661,7 +914,7 @@ uint32_t grid_for(int64_t work, int wg, uint32_t cap) {
 void launch_graph_stats(const gsm_graph &g, hipStream_t s) {
   if (g.n == 0) return;
   hipLaunchKernelGGL(k_graph_stats, dim3(grid_for(g.n * 16, 256, 1u << 16)), dim3(256), 0, s,
-                     g.rp, g.col, g.lab, g.n, g.deg, g.ne0);
+                     g.rp, g.col, g.lab, g.n, g.deg, g.ne0, g.dne);
   GSM_HIP(hipGetLastError());
 }
 
@@ -701,6 +954,37 @@ void launch_scan(const uint32_t *W, const uint64_t *n_dev, uint64_t *S, uint64_t
   hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(kScanWG), 0, s, W, n_dev, scratch);
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanWG), 0, s, scratch, n_dev, S, total_out);
   hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kScanWG), 0, s, W, n_dev, scratch, S);
+  GSM_HIP(hipGetLastError());
+}
+
+void launch_filter_init_batch(const DeviceGraph &g, const QueryArgs *qa_dev, int nq, uint16_t *cmask,
+                              hipStream_t s) {
+  if (g.n == 0 || nq == 0) return;
+  hipLaunchKernelGGL(k_filter_init_batch, dim3(grid_for(g.n, 256, 1024), nq), dim3(256), 0, s, g, qa_dev,
+                     cmask);
+  GSM_HIP(hipGetLastError());
+}
+
+void launch_filter_refine_batch(const DeviceGraph &g, const int32_t *heavy, int64_t nheavy,
+                                const QueryArgs *qa_dev, int nq, const uint16_t *prev, uint16_t *next,
+                                hipStream_t s) {
+  if (g.n == 0 || nq == 0) return;
+  hipLaunchKernelGGL(k_refine_light_batch, dim3(grid_for(g.n * 16, 256, 2048), nq), dim3(256), 0, s, g,
+                     qa_dev, prev, next);
+  GSM_HIP(hipGetLastError());
+  if (nheavy > 0) {
+    hipLaunchKernelGGL(k_refine_heavy_batch, dim3(grid_for(nheavy * 256, 256, 1024), nq), dim3(256), 0, s,
+                       g, qa_dev, heavy, nheavy, prev, next);
+    GSM_HIP(hipGetLastError());
+  }
+}
+
+void launch_compact_first_batch(const DeviceGraph &g, const FirstBatch *fb_dev, int nq, int32_t *rows,
+                                uint16_t *qid, uint32_t *W, int64_t *abase, uint8_t *apos,
+                                uint64_t *counter, uint64_t *counts, uint64_t *pairs1, hipStream_t s) {
+  if (g.n == 0 || nq == 0) return;
+  hipLaunchKernelGGL(k_compact_first_batch, dim3(grid_for(g.n, 256, 1024), nq), dim3(256), 0, s, g, fb_dev,
+                     rows, qid, W, abase, apos, counter, counts, pairs1);
   GSM_HIP(hipGetLastError());
 }
 

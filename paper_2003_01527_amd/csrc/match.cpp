@@ -106,7 +106,7 @@ struct Matcher {
   Matcher(gsm_graph &g_, const gsm_query &q_, const Options &o_, Workspace &ws_)
       : g(g_), qh(q_), o(o_), ws(ws_), s(o_.stream) {
     p = make_plan(g, qh);
-    dg = DeviceGraph{g.rp,  g.col,  g.lab, g.deg, g.ne0, g.col_lab ? g.col_lab : g.col,
+    dg = DeviceGraph{g.rp,  g.col,  g.lab, g.deg, g.ne0, g.dne, g.col_lab ? g.col_lab : g.col,
                      g.loff, g.loff_stride, g.n};
     dcnt = ws.counters.as<uint64_t>();
     std::memset(&st, 0, sizeof(st));
@@ -408,6 +408,20 @@ Workspace &acquire_ws(gsm_graph &g) {
 
 }  // namespace
 
+uint64_t match_count_one(gsm_graph &g, const gsm_query &q, const gsm_match_opts &oo, Workspace &ws) {
+  Options o = read_opts(&oo, q.q);
+  o.emit = nullptr;
+  o.emit_ctx = nullptr;
+  o.rows_dev = false;
+  o.stats = nullptr;
+  o.root_q = -1;
+  Matcher m(g, q, o, ws);
+  m.plan_capacity();
+  const uint64_t c = m.run();
+  m.sync();
+  return c;
+}
+
 }  // namespace gsm
 
 using gsm::Error;
@@ -507,19 +521,6 @@ gsm_status gsm_match_min_budget(gsm_graph_t g, gsm_query_t qh, int32_t host_rows
     gsm::set_error(e.msg);
     return e.status;
   }
-}
-
-gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query_t *qs,
-                           const gsm_match_opts *opts, uint64_t *counts) {
-  if (!g || nq < 0 || (nq > 0 && (!qs || !counts))) {
-    gsm::set_error("gsm_match_batch: invalid arguments");
-    return GSM_E_INVALID_ARG;
-  }
-  for (int32_t k = 0; k < nq; ++k) {
-    gsm_status st = gsm_match(g, qs[k], opts, &counts[k], nullptr, 0, nullptr);
-    if (st != GSM_OK) return st;
-  }
-  return GSM_OK;
 }
 
 }  // extern "C"

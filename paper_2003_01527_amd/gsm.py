@@ -69,7 +69,7 @@ class MatchOpts(ctypes.Structure):
                 ("emit", EMIT_FN), ("emit_ctx", ctypes.c_void_p),
                 ("stats", ctypes.POINTER(Stats)), ("tile_items", ctypes.c_int32),
                 ("wg_size", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("batch_heavy_pairs", ctypes.c_uint64)]
 
 
 def library_path() -> str:
@@ -203,7 +203,8 @@ class Query:
 
 def make_opts(budget: int = 0, filter_rounds: int = 1, use_degree: bool = True, use_ne: bool = True,
               stream=None, root=None, tile_items: int = 0, wg_size: int = 0, profile: bool = False,
-              stats: Optional[Stats] = None, stage_output: bool = True) -> MatchOpts:
+              stats: Optional[Stats] = None, stage_output: bool = True,
+              batch_heavy_pairs: int = 0) -> MatchOpts:
     o = MatchOpts()
     _load().gsm_match_opts_init(ctypes.byref(o))
     o.memory_budget_bytes = int(budget)
@@ -218,6 +219,7 @@ def make_opts(budget: int = 0, filter_rounds: int = 1, use_degree: bool = True, 
     o.wg_size = int(wg_size)
     o.profile = 1 if profile else 0
     o.flags = 0 if stage_output else 1
+    o.batch_heavy_pairs = int(batch_heavy_pairs)
     if stats is not None:
         stats.struct_size = ctypes.sizeof(Stats)
         o.stats = ctypes.pointer(stats)
