@@ -219,6 +219,49 @@ gsm_status gsm_match_min_budget(gsm_graph_t g, gsm_query_t qh, int32_t host_rows
 gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query_t *qs,
                            const gsm_match_opts *opts, uint64_t *counts);
 
+/* ---------------------------------------------------------------- serving -- */
+
+/*
+ * A serving engine over one resident graph: queries are submitted as they
+ * arrive and matched (count only) by worker threads, each with its own HIP
+ * stream and workspace, so batches of different workers overlap on the
+ * device.  A free worker takes the oldest waiting queries that fit the device
+ * memory still free (each query reserves its frontier estimate: its first
+ * level's neighbour total for its second vertex's label times the row size,
+ * clamped to [per_query_min, per_query_budget]) and matches them as one
+ * batch; queries that arrive meanwhile join the next batch a worker forms.
+ * The memory-bounded expansion keeps every query within its reservation.
+ */
+typedef struct gsm_server_opts {
+  uint32_t struct_size;
+  uint64_t arena_bytes;       /* device memory shared by in-flight queries (0 = 16 GiB) */
+  uint64_t per_query_budget;  /* largest reservation of one query (0 = 4 GiB) */
+  int32_t workers;            /* worker threads / streams (0 = 2) */
+  int32_t max_batch;          /* queries per batch (0 = 64) */
+  int32_t max_active;         /* queries admitted at once (0 = 1024) */
+  int32_t wg_size, tile_items;
+  uint64_t batch_heavy_pairs; /* as in gsm_match_opts */
+} gsm_server_opts;
+
+typedef struct gsm_result {
+  gsm_status status;
+  uint64_t count;
+  uint64_t t_submit_ns, t_admit_ns, t_done_ns; /* steady-clock nanoseconds */
+  int32_t batch_size;                          /* queries in the batch that ran it */
+} gsm_result;
+
+void gsm_server_opts_init(gsm_server_opts *o);
+/* The graph must outlive the server. */
+gsm_status gsm_server_create(gsm_graph_t g, const gsm_server_opts *opts, gsm_server_t *out);
+/* Copies the query (the caller may destroy it on return); *ticket identifies the request. */
+gsm_status gsm_server_submit(gsm_server_t srv, gsm_query_t qh, uint64_t *ticket);
+/* Waits for a ticket (timeout_ms < 0: forever) and releases it.  GSM_E_TIMEOUT if not done. */
+gsm_status gsm_server_wait(gsm_server_t srv, uint64_t ticket, int32_t timeout_ms, gsm_result *out);
+/* Finishes the admitted work, stops the workers, frees everything. */
+void gsm_server_destroy(gsm_server_t srv);
+/* Steady-clock time in nanoseconds (the clock of gsm_result's timestamps). */
+uint64_t gsm_now_ns(void);
+
 /* ----------------------------------------------------------------- errors -- */
 
 const char *gsm_status_str(gsm_status s);

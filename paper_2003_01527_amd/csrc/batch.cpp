@@ -123,6 +123,22 @@ struct BatchMatcher {
     if (budget < fixed + 64) throw Error{GSM_E_BUDGET, "memory budget below the first frontiers"};
     const uint64_t rest = budget - fixed;
     const int shares = std::max(1, maxq - 2);
+    // buffers kept from earlier calls count against this budget
+    uint64_t held = ws.emit.bytes + ws.tables.bytes + ws.counts.bytes;
+    for (int i = 0; i < kMaxQ; ++i)
+      held += ws.rows[i].bytes + ws.S[i].bytes + ws.W[i].bytes + ws.apos[i].bytes + ws.abase[i].bytes +
+              ws.qid[i].bytes;
+    if (held > budget) {
+      for (int i = 0; i < kMaxQ; ++i) {
+        ws.rows[i].release();
+        ws.S[i].release();
+        ws.W[i].release();
+        ws.apos[i].release();
+        ws.abase[i].release();
+        ws.qid[i].release();
+      }
+      ws.emit.release();
+    }
     for (int i = 0; i < kMaxQ; ++i) cap[i] = 0;
     cap[1] = first;
     for (int i = 2; i < maxq; ++i) {
@@ -213,6 +229,49 @@ struct BatchMatcher {
 
 }  // namespace
 
+void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_match_opts &o,
+                    Workspace &ws, uint64_t *counts, uint64_t *launches_out) {
+    const hipStream_t stream = (hipStream_t)o.hip_stream;
+    auto configure = [&](BatchMatcher &m) {
+      m.rounds = o.filter_rounds;
+      m.use_deg = o.use_degree;
+      m.use_ne = o.use_ne;
+      m.wg = o.wg_size ? o.wg_size : 512;
+      m.items = o.tile_items ? o.tile_items : 4;
+      m.budget = o.memory_budget_bytes ? o.memory_budget_bytes : (uint64_t(4) << 30);
+    };
+    // split: heavy queries on launches of their own, the rest shared
+    const uint64_t heavy_pairs = o.batch_heavy_pairs ? o.batch_heavy_pairs : (uint64_t(1) << 18);
+    std::vector<int> light;
+    std::vector<int> heavy;
+    {
+      BatchMatcher est(g, qs, nq, ws, stream);
+      configure(est);
+      const std::vector<uint64_t> p1 = est.first_level_pairs();
+      for (int k = 0; k < nq; ++k) (qs[k]->q > 1 && p1[k] > heavy_pairs ? heavy : light).push_back(k);
+    }
+    uint64_t launches = 0;
+    for (int k : heavy) counts[k] = match_count_one(g, *qs[k], o, ws);
+    // the shared launches group queries of one size, so every level of a group
+    // either writes the next frontier for all its rows or counts all of them
+    for (int qsize = 1; qsize <= kMaxQ; ++qsize) {
+      std::vector<int> grp;
+      for (int k : light)
+        if (qs[k]->q == qsize) grp.push_back(k);
+      if (grp.empty()) continue;
+      std::vector<const gsm_query *> sub;
+      for (int k : grp) sub.push_back(qs[k]);
+      std::vector<uint64_t> c(grp.size());
+      BatchMatcher m(g, sub.data(), (int)sub.size(), ws, stream);
+      configure(m);
+      m.plan_capacity();
+      m.run(c.data());
+      launches += m.launches;
+      for (size_t j = 0; j < grp.size(); ++j) counts[grp[j]] = c[j];
+    }
+    if (launches_out) *launches_out = launches;
+}
+
 }  // namespace gsm
 
 using gsm::Error;
@@ -244,50 +303,9 @@ extern "C" gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query
     if (o.filter_rounds < 0 || o.filter_rounds > 64) throw Error{GSM_E_INVALID_ARG, "filter_rounds out of [0, 64]"};
     std::lock_guard<std::mutex> lk(g->mu);
     if (!g->ws) g->ws = new gsm::Workspace();
-    gsm::Workspace &ws = *g->ws;
-    const hipStream_t stream = (hipStream_t)o.hip_stream;
-    auto configure = [&](gsm::BatchMatcher &m) {
-      m.rounds = o.filter_rounds;
-      m.use_deg = o.use_degree;
-      m.use_ne = o.use_ne;
-      m.wg = o.wg_size ? o.wg_size : 512;
-      m.items = o.tile_items ? o.tile_items : 4;
-      m.budget = o.memory_budget_bytes ? o.memory_budget_bytes : (uint64_t(4) << 30);
-    };
-    // split: heavy queries on launches of their own, the rest shared
-    const uint64_t heavy_pairs = o.batch_heavy_pairs ? o.batch_heavy_pairs : (uint64_t(1) << 18);
-    std::vector<int> light;
-    std::vector<int> heavy;
-    {
-      gsm::BatchMatcher est(*g, qs, nq, ws, stream);
-      configure(est);
-      const std::vector<uint64_t> p1 = est.first_level_pairs();
-      for (int k = 0; k < nq; ++k) (qs[k]->q > 1 && p1[k] > heavy_pairs ? heavy : light).push_back(k);
-    }
     uint64_t launches = 0;
-    for (int k : heavy) counts[k] = gsm::match_count_one(*g, *qs[k], o, ws);
-    // the shared launches group queries of one size, so every level of a group
-    // either writes the next frontier for all its rows or counts all of them
-    for (int qsize = 1; qsize <= gsm::kMaxQ; ++qsize) {
-      std::vector<int> grp;
-      for (int k : light)
-        if (qs[k]->q == qsize) grp.push_back(k);
-      if (grp.empty()) continue;
-      std::vector<const gsm_query *> sub;
-      for (int k : grp) sub.push_back(qs[k]);
-      std::vector<uint64_t> c(grp.size());
-      gsm::BatchMatcher m(*g, sub.data(), (int)sub.size(), ws, stream);
-      configure(m);
-      m.plan_capacity();
-      m.run(c.data());
-      launches += m.launches;
-      for (size_t j = 0; j < grp.size(); ++j) counts[grp[j]] = c[j];
-    }
-    if (o.stats) {
-      o.stats->expand_launches = launches;
-      o.stats->chunks[0] = heavy.size();
-      o.stats->chunks[1] = light.size();
-    }
+    gsm::match_batch_on(*g, qs, nq, o, *g->ws, counts, &launches);
+    if (o.stats) o.stats->expand_launches = launches;
     return GSM_OK;
   } catch (const Error &e) {
     gsm::set_error(e.msg);

@@ -239,6 +239,12 @@ void launch_compact_first_batch(const DeviceGraph &g, const FirstBatch *fb_dev,
                                 hipStream_t s);
 // Count-only match of one query on the workspace (the single-query driver).
 uint64_t match_count_one(gsm_graph &g, const gsm_query &q, const gsm_match_opts &o, Workspace &ws);
+// Smallest batched budget for nq queries of q vertices (first frontiers at
+// n rows each, one row per further level).
+uint64_t min_budget_bytes_batch(const gsm_graph &g, int nq, int q);
+// Counts of a set of queries on the workspace (the batched driver, no locking).
+void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_match_opts &o,
+                    Workspace &ws, uint64_t *counts, uint64_t *launches);
 
 // -------------------------------------------------------------- workspace --
 

@@ -114,6 +114,16 @@ def _load():
     lib.gsm_match.argtypes = [vp, vp, P(MatchOpts), P(u64), vp, u64, P(u64)]
     lib.gsm_match_min_budget.restype = ctypes.c_int
     lib.gsm_match_min_budget.argtypes = [vp, vp, i32, P(u64)]
+    lib.gsm_server_opts_init.argtypes = [P(ServerOpts)]
+    lib.gsm_server_create.restype = ctypes.c_int
+    lib.gsm_server_create.argtypes = [vp, P(ServerOpts), P(vp)]
+    lib.gsm_server_submit.restype = ctypes.c_int
+    lib.gsm_server_submit.argtypes = [vp, vp, P(u64)]
+    lib.gsm_server_wait.restype = ctypes.c_int
+    lib.gsm_server_wait.argtypes = [vp, u64, i32, P(Result)]
+    lib.gsm_server_destroy.argtypes = [vp]
+    lib.gsm_now_ns.restype = u64
+    lib.gsm_now_ns.argtypes = []
     lib.gsm_match_batch.restype = ctypes.c_int
     lib.gsm_match_batch.argtypes = [vp, i32, P(vp), P(MatchOpts), P(u64)]
     _lib = lib
@@ -293,6 +303,63 @@ def match(graph: Graph, query: Query, rows=None, rows_cap: Optional[int] = None,
     if isinstance(out, np.ndarray):
         out = out[:int(written.value)]
     return count, out, st.as_dict()
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("arena_bytes", ctypes.c_uint64),
+                ("per_query_budget", ctypes.c_uint64), ("workers", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("wg_size", ctypes.c_int32), ("tile_items", ctypes.c_int32),
+                ("batch_heavy_pairs", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("count", ctypes.c_uint64), ("t_submit_ns", ctypes.c_uint64),
+                ("t_admit_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64),
+                ("batch_size", ctypes.c_int32)]
+
+
+class Server:
+    """Serving engine over a resident graph (gsm_server_*)."""
+
+    def __init__(self, graph: Graph, arena_bytes: int = 0, per_query_budget: int = 0, workers: int = 0,
+                 max_batch: int = 0, max_active: int = 0, wg_size: int = 0, tile_items: int = 0,
+                 batch_heavy_pairs: int = 0):
+        lib = _load()
+        o = ServerOpts()
+        lib.gsm_server_opts_init(ctypes.byref(o))
+        o.arena_bytes, o.per_query_budget = int(arena_bytes), int(per_query_budget)
+        o.workers, o.max_batch, o.max_active = int(workers), int(max_batch), int(max_active)
+        o.wg_size, o.tile_items, o.batch_heavy_pairs = int(wg_size), int(tile_items), int(batch_heavy_pairs)
+        self._graph = graph  # keeps the graph alive while the server runs
+        self._h = ctypes.c_void_p()
+        _check(lib.gsm_server_create(graph._h, ctypes.byref(o), ctypes.byref(self._h)))
+
+    def submit(self, query: Query) -> int:
+        t = ctypes.c_uint64()
+        _check(_load().gsm_server_submit(self._h, query._h, ctypes.byref(t)))
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> dict:
+        r = Result()
+        _check(_load().gsm_server_wait(self._h, ticket, timeout_ms, ctypes.byref(r)))
+        return {"count": int(r.count), "t_submit_ns": int(r.t_submit_ns), "t_admit_ns": int(r.t_admit_ns),
+                "t_done_ns": int(r.t_done_ns), "batch_size": int(r.batch_size)}
+
+    def close(self):
+        if self._h:
+            _load().gsm_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def now_ns() -> int:
+    return int(_load().gsm_now_ns())
 
 
 def min_budget(graph: Graph, query: Query, host_rows: bool = False) -> int:
