@@ -38,6 +38,8 @@ struct BatchMatcher {
   FirstBatch *d_fb = nullptr;
   uint64_t *d_counts = nullptr;
   uint64_t launches = 0;
+  uint64_t level_pairs[kMaxQ] = {0};
+  uint64_t level_rows[kMaxQ] = {0};
 
   BatchMatcher(gsm_graph &g_, const gsm_query *const *q_, int nq_, Workspace &ws_, hipStream_t s_)
       : g(g_), qs(q_, q_ + nq_), ws(ws_), s(s_), nq(nq_) {
@@ -162,6 +164,8 @@ struct BatchMatcher {
     fetch_counters();
     const uint64_t N = ws.h_counters[kCntRows + i];
     const uint64_t P = ws.h_counters[kCntPairs + i];
+    level_rows[i] += N;
+    level_pairs[i] += P;
     if (P == 0) return;
     ExpandArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -230,7 +234,7 @@ struct BatchMatcher {
 }  // namespace
 
 void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_match_opts &o,
-                    Workspace &ws, uint64_t *counts, uint64_t *launches_out) {
+                    Workspace &ws, uint64_t *counts, uint64_t *launches_out, gsm_stats *st) {
     const hipStream_t stream = (hipStream_t)o.hip_stream;
     auto configure = [&](BatchMatcher &m) {
       m.rounds = o.filter_rounds;
@@ -267,6 +271,11 @@ void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_
       m.plan_capacity();
       m.run(c.data());
       launches += m.launches;
+      if (st)
+        for (int i = 0; i < kMaxQ; ++i) {
+          st->pairs[i] += m.level_pairs[i];
+          if (i > 0) st->rows[i - 1] += m.level_rows[i];
+        }
       for (size_t j = 0; j < grp.size(); ++j) counts[grp[j]] = c[j];
     }
     if (launches_out) *launches_out = launches;
@@ -304,8 +313,16 @@ extern "C" gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query
     std::lock_guard<std::mutex> lk(g->mu);
     if (!g->ws) g->ws = new gsm::Workspace();
     uint64_t launches = 0;
-    gsm::match_batch_on(*g, qs, nq, o, *g->ws, counts, &launches);
-    if (o.stats) o.stats->expand_launches = launches;
+    gsm_stats st;
+    std::memset(&st, 0, sizeof(st));
+    gsm::match_batch_on(*g, qs, nq, o, *g->ws, counts, &launches, &st);
+    if (o.stats) {
+      st.expand_launches = launches;
+      const uint32_t sz = std::min<uint32_t>(o.stats->struct_size ? o.stats->struct_size : sizeof(gsm_stats),
+                                             sizeof(gsm_stats));
+      std::memcpy(o.stats, &st, sz);
+      o.stats->struct_size = sz;
+    }
     return GSM_OK;
   } catch (const Error &e) {
     gsm::set_error(e.msg);

@@ -244,7 +244,7 @@ uint64_t match_count_one(gsm_graph &g, const gsm_query &q, const gsm_match_opts 
 uint64_t min_budget_bytes_batch(const gsm_graph &g, int nq, int q);
 // Counts of a set of queries on the workspace (the batched driver, no locking).
 void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_match_opts &o,
-                    Workspace &ws, uint64_t *counts, uint64_t *launches);
+                    Workspace &ws, uint64_t *counts, uint64_t *launches, gsm_stats *st);
 
 // -------------------------------------------------------------- workspace --
 

@@ -629,58 +629,78 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
       constexpr bool UNI = decltype(uni_tag)::value;
       BatchLevel ubl{};
       if (BATCHED && UNI) ubl = a.blev[q0 * kMaxQ + i];  // uniform address: scalar loads
+      // level parameters of every item
+      uint32_t p_nbr[ITEMS], p_next_nbr[ITEMS], p_last[ITEMS];
+      int32_t p_next_label[ITEMS];
+      bool cand[ITEMS];
+      if (BATCHED) {
+        BatchLevel bl[ITEMS];
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) bl[it] = UNI ? ubl : a.blev[qk[it] * kMaxQ + i];
+        // candidate test: every item's load issued before any is used
+        uint2 dn[ITEMS];
+        int32_t lv[ITEMS];
+        const bool label_known = a.g.loff != nullptr;
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+          dn[it] = a.g.dne[wv[it]];
+          lv[it] = (!label_known && a.g.lab) ? a.g.lab[wv[it]] : 0;
+        }
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+          p_nbr[it] = bl[it].nbr_mask;
+          p_next_nbr[it] = bl[it].next_nbr_mask;
+          p_next_label[it] = bl[it].next_label;
+          p_last[it] = (MODE == kModeBatchLast);
+          cand[it] = dn[it].x >= bl[it].qdeg && (uint64_t)dn[it].y >= bl[it].qne &&
+                     (label_known || lv[it] == bl[it].qlab);
+        }
+      } else {
+        uint32_t cm[ITEMS];
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) cm[it] = a.cmask[wv[it]];
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+          p_nbr[it] = a.L.nbr_mask;
+          p_next_nbr[it] = a.L.next_nbr_mask;
+          p_next_label[it] = a.L.next_label;
+          p_last[it] = (MODE != kModeNext);
+          cand[it] = (cm[it] >> a.L.qbit) & 1;
+        }
+      }
 #pragma unroll
       for (int it = 0; it < ITEMS; ++it) {
-        uint32_t p_nbr, p_next_nbr, p_qbit, p_last;
-        int32_t p_next_label;
-        bool cand;
-        if (BATCHED) {
-          const BatchLevel bl = UNI ? ubl : a.blev[qk[it] * kMaxQ + i];
-          p_nbr = bl.nbr_mask;
-          p_next_nbr = bl.next_nbr_mask;
-          p_next_label = bl.next_label;
-          p_qbit = bl.qbit;
-          p_last = (MODE == kModeBatchLast);
-          cand = inline_candidate(a.g, wv[it], bl.qlab, bl.qdeg, bl.qne, a.g.loff != nullptr);
-        } else {
-          p_nbr = a.L.nbr_mask;
-          p_next_nbr = a.L.next_nbr_mask;
-          p_next_label = a.L.next_label;
-          p_qbit = a.L.qbit;
-          p_last = (MODE != kModeNext);
-          cand = (a.cmask[wv[it]] >> p_qbit) & 1;
-        }
         nW[it] = 0;
         nbase[it] = 0;
         napos[it] = 0;
         const bool valid = (uint32_t)(it * WG + tid) < len;
         const int32_t w = wv[it];
         const uint32_t k = rk[it];
-        bool keep = valid && cand;
-        const uint32_t inj = ((1u << i) - 1u) & ~p_nbr;
+        bool keep = valid && cand[it];
+        const uint32_t inj = ((1u << i) - 1u) & ~p_nbr[it];
         for (uint32_t m = inj; m; m &= m - 1) {
           const int j = __builtin_ctz(m);
           const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
           keep = keep && (x != w);
         }
-        for (uint32_t m = p_nbr; m; m &= m - 1) {
+        for (uint32_t m = p_nbr[it]; m; m &= m - 1) {
           const int j = __builtin_ctz(m);
           if (keep && j != ap[it]) {
             const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
             keep = has_edge(a.g, x, w, probes);
           }
         }
-        if ((MODE == kModeNext || MODE == kModeBatch) && keep && !p_last) {
+        if ((MODE == kModeNext || MODE == kModeBatch) && keep && !p_last[it]) {
           // anchor of the next position: the earlier neighbour with the fewest
           // neighbours of the next label; an empty range ends the row here
           uint32_t best = 0xffffffffu;
           int bj = 0;
           int64_t bb = 0;
-          for (uint32_t mm = p_next_nbr; mm; mm &= mm - 1) {
+          for (uint32_t mm = p_next_nbr[it]; mm; mm &= mm - 1) {
             const int j = __builtin_ctz(mm);
             const int32_t x = (j == i) ? w : (stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j]);
             int64_t base;
-            const uint32_t d = label_range(a.g, x, p_next_label, base);
+            const uint32_t d = label_range(a.g, x, p_next_label[it], base);
             if (d < best) {
               best = d;
               bj = j;
@@ -842,8 +862,28 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
     block_excl_scan<WG>(wg_count, sw, &total);
     if (tid == 0 && total) atomicAdd((unsigned long long *)a.counter, (unsigned long long)total);
   }
-  if (MODE == kModeBatchLast && lane == 0 && acc_c)
-    atomicAdd((unsigned long long *)(a.counts + acc_k), (unsigned long long)acc_c);
+  if (MODE == kModeBatchLast) {
+    // merge the waves' pending (query, count) pairs, one atomic per query
+    __shared__ uint32_t s_acck[NW];
+    __shared__ uint64_t s_accc[NW];
+    if (lane == 0) {
+      s_acck[wid] = acc_k;
+      s_accc[wid] = acc_c;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w1 = 0; w1 < NW; ++w1) {
+        if (!s_accc[w1]) continue;
+        uint64_t c = s_accc[w1];
+        for (int w2 = w1 + 1; w2 < NW; ++w2)
+          if (s_acck[w2] == s_acck[w1]) {
+            c += s_accc[w2];
+            s_accc[w2] = 0;
+          }
+        atomicAdd((unsigned long long *)(a.counts + s_acck[w1]), (unsigned long long)c);
+      }
+    }
+  }
   if (a.probes) {
     uint64_t total;
     block_excl_scan<WG>(probes, sw, &total);
@@ -858,8 +898,10 @@ void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
   constexpr uint64_t TILE = (uint64_t)WG * ITEMS;
   const uint64_t ntiles = (a.pair_end - a.pair_begin + TILE - 1) / TILE;
   if (ntiles == 0) return;
+  // persistent-style grid: a few workgroups per CU loop over the tiles, so
+  // per-workgroup reductions end in few atomics
   uint64_t grid = ntiles;
-  const uint64_t kMaxGrid = 1u << 20;
+  const uint64_t kMaxGrid = 8192;
   if (grid > kMaxGrid) grid = kMaxGrid;
   if (grid >= 8) grid &= ~7ull;
   const int width = (mode == kModeNext || mode == kModeBatch) ? a.L.i + 1 : a.L.q;

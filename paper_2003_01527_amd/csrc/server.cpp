@@ -103,7 +103,7 @@ struct gsm_server {
         mo.wg_size = o.wg_size;
         mo.tile_items = o.tile_items;
         mo.batch_heavy_pairs = o.batch_heavy_pairs;
-        gsm::match_batch_on(*g, qs.data(), (int)qs.size(), mo, *ws, counts.data(), nullptr);
+        gsm::match_batch_on(*g, qs.data(), (int)qs.size(), mo, *ws, counts.data(), nullptr, nullptr);
       } catch (const gsm::Error &e) {
         st = e.status;
         err = e.msg;

@@ -368,10 +368,10 @@ def min_budget(graph: Graph, query: Query, host_rows: bool = False) -> int:
     return int(b.value)
 
 
-def match_batch(graph: Graph, queries: Sequence[Query], **kw) -> np.ndarray:
+def match_batch(graph: Graph, queries: Sequence[Query], stats: Optional[Stats] = None, **kw) -> np.ndarray:
     counts = np.zeros(len(queries), dtype=np.uint64)
     arr = (ctypes.c_void_p * max(1, len(queries)))(*[q._h for q in queries])
-    o = make_opts(**kw)
+    o = make_opts(stats=stats, **kw)
     _check(_load().gsm_match_batch(graph._h, len(queries), arr, ctypes.byref(o),
                                    counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
     return counts
