@@ -33,7 +33,6 @@ struct BatchMatcher {
   DeviceGraph dg;
   uint64_t cap[kMaxQ];
   uint64_t *dcnt;
-  QueryArgs *d_qa = nullptr;
   BatchLevel *d_bl = nullptr;
   FirstBatch *d_fb = nullptr;
   uint64_t *d_counts = nullptr;
@@ -60,23 +59,10 @@ struct BatchMatcher {
   }
 
   void upload_tables() {
-    std::vector<QueryArgs> qa(nq);
     std::vector<BatchLevel> bl((size_t)nq * kMaxQ);
     std::vector<FirstBatch> fb(nq);
     for (int k = 0; k < nq; ++k) {
       const Plan &p = plans[k];
-      QueryArgs &a = qa[k];
-      std::memset(&a, 0, sizeof(a));
-      a.q = p.q;
-      a.root_bit = -1;
-      a.root_mod = 1;
-      a.use_deg = use_deg;
-      a.use_ne = use_ne;
-      for (int u = 0; u < p.q; ++u) {
-        a.qlab[u] = p.qlab[u];
-        a.qdeg[u] = (uint32_t)p.qdeg[u];
-        a.qne[u] = p.qne[u];
-      }
       for (int i = 0; i < p.q; ++i) {
         BatchLevel &e = bl[(size_t)k * kMaxQ + i];
         e.nbr_mask = p.backmask[i];
@@ -96,16 +82,13 @@ struct BatchMatcher {
       fb[k].label1 = (p.q > 1) ? p.qlab[p.order[1]] : 0;
       fb[k].single = (p.q == 1) ? 1 : 0;
     }
-    const size_t b_qa = nq * sizeof(QueryArgs), b_bl = bl.size() * sizeof(BatchLevel),
-                 b_fb = nq * sizeof(FirstBatch);
-    const size_t o_bl = (b_qa + 255) & ~size_t(255), o_fb = (o_bl + b_bl + 255) & ~size_t(255);
+    const size_t b_bl = bl.size() * sizeof(BatchLevel), b_fb = nq * sizeof(FirstBatch);
+    const size_t o_fb = (b_bl + 255) & ~size_t(255);
     ws.tables.reserve(o_fb + b_fb);
     char *base = ws.tables.as<char>();
-    GSM_HIP(hipMemcpyAsync(base, qa.data(), b_qa, hipMemcpyHostToDevice, s));
-    GSM_HIP(hipMemcpyAsync(base + o_bl, bl.data(), b_bl, hipMemcpyHostToDevice, s));
+    GSM_HIP(hipMemcpyAsync(base, bl.data(), b_bl, hipMemcpyHostToDevice, s));
     GSM_HIP(hipMemcpyAsync(base + o_fb, fb.data(), b_fb, hipMemcpyHostToDevice, s));
-    d_qa = reinterpret_cast<QueryArgs *>(base);
-    d_bl = reinterpret_cast<BatchLevel *>(base + o_bl);
+    d_bl = reinterpret_cast<BatchLevel *>(base);
     d_fb = reinterpret_cast<FirstBatch *>(base + o_fb);
     ws.counts.reserve(std::max(nq, 1) * sizeof(uint64_t));
     d_counts = ws.counts.as<uint64_t>();

@@ -129,6 +129,7 @@ struct LevelArgs {
   uint32_t next_nbr_mask;  // positions j <= i adjacent to position i+1 (0 at the last level)
   int32_t next_label;      // label of position i+1
   int32_t out_col[kMaxQ];  // emit: output column (query id) of position j
+  int32_t in_pos[kMaxQ];   // emit: position of output column (query id) c
 };
 
 // --------------------------------------------------------------- kernels --
@@ -218,12 +219,6 @@ struct ExpandArgs {
 
 void launch_expand(const ExpandArgs &a, int mode, int wg, int items, hipStream_t s);
 
-// Batched filter and first frontier: query k's candidate mask is cmask + k*n.
-void launch_filter_init_batch(const DeviceGraph &g, const QueryArgs *qa_dev, int nq, uint16_t *cmask,
-                              hipStream_t s);
-void launch_filter_refine_batch(const DeviceGraph &g, const int32_t *heavy, int64_t nheavy,
-                                const QueryArgs *qa_dev, int nq, const uint16_t *prev, uint16_t *next,
-                                hipStream_t s);
 // First frontier of every query: rows tagged with the query id; queries with a
 // single vertex are counted into counts[k] directly.
 struct FirstBatch {

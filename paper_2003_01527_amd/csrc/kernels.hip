@@ -261,91 +261,7 @@ __global__ __launch_bounds__(256) void k_compact_first(DeviceGraph g, const uint
   }
 }
 
-// ---------------------------------------------------- batched filter --
-
-__global__ void k_filter_init_batch(DeviceGraph g, const QueryArgs *qa_all, uint16_t *cmask) {
-  __shared__ QueryArgs qa;
-  if (threadIdx.x == 0) qa = qa_all[blockIdx.y];
-  __syncthreads();
-  uint16_t *cm = cmask + (int64_t)blockIdx.y * g.n;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
-    const int32_t lv = g.lab ? g.lab[v] : 0;
-    const uint32_t d = g.deg[v];
-    const uint64_t ne = g.ne0 ? g.ne0[v] : (uint64_t)d;
-    cm[v] = candidate_bits(qa, lv, d, ne, (uint64_t)v);
-  }
-}
-
-__global__ void k_refine_light_batch(DeviceGraph g, const QueryArgs *qa_all, const uint16_t *prev_all,
-                                     uint16_t *next_all) {
-  __shared__ QueryArgs qa;
-  if (threadIdx.x == 0) qa = qa_all[blockIdx.y];
-  __syncthreads();
-  const uint16_t *prev = prev_all + (int64_t)blockIdx.y * g.n;
-  uint16_t *next = next_all + (int64_t)blockIdx.y * g.n;
-  constexpr int G = 16;
-  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int sub = threadIdx.x & (G - 1);
-  for (int64_t v = gid / G; v < g.n; v += nthreads / G) {
-    const uint16_t pm = prev[v];
-    const int64_t b = g.rp[v], e = g.rp[v + 1];
-    if (e - b > kHeavyDegree) continue;
-    if (pm == 0) {
-      if (sub == 0) next[v] = 0;
-      continue;
-    }
-    uint32_t c = 0;
-    uint64_t s = 0;
-    for (int64_t k = b + sub; k < e; k += G) {
-      const int32_t w = g.col[k];
-      if (prev[w]) {
-        c += 1;
-        s += g.lab ? (uint64_t)g.lab[w] + 1 : 1;
-      }
-    }
-#pragma unroll
-    for (int d = G / 2; d > 0; d >>= 1) {
-      c += __shfl_xor(c, d, G);
-      s += __shfl_xor(s, d, G);
-    }
-    if (sub == 0) next[v] = refine_bits(qa, pm, c, s);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_refine_heavy_batch(DeviceGraph g, const QueryArgs *qa_all,
-                                                            const int32_t *heavy, int64_t nheavy,
-                                                            const uint16_t *prev_all,
-                                                            uint16_t *next_all) {
-  __shared__ QueryArgs qa;
-  __shared__ uint64_t sw[256 / kWave];
-  if (threadIdx.x == 0) qa = qa_all[blockIdx.y];
-  __syncthreads();
-  const uint16_t *prev = prev_all + (int64_t)blockIdx.y * g.n;
-  uint16_t *next = next_all + (int64_t)blockIdx.y * g.n;
-  for (int64_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
-    const int32_t v = heavy[h];
-    const uint16_t pm = prev[v];
-    if (pm == 0) {
-      if (threadIdx.x == 0) next[v] = 0;
-      continue;
-    }
-    const int64_t b = g.rp[v], e = g.rp[v + 1];
-    uint64_t c = 0, s = 0;
-    for (int64_t k = b + threadIdx.x; k < e; k += blockDim.x) {
-      const int32_t w = g.col[k];
-      if (prev[w]) {
-        c += 1;
-        s += g.lab ? (uint64_t)g.lab[w] + 1 : 1;
-      }
-    }
-    uint64_t tc, ts;
-    block_excl_scan<256>(c, sw, &tc);
-    block_excl_scan<256>(s, sw, &ts);
-    if (threadIdx.x == 0) next[v] = refine_bits(qa, pm, (uint32_t)tc, ts);
-  }
-}
+// ------------------------------------------------ batched first frontier --
 
 // Round-0 candidate test without a per-query array: one 8-byte load of
 // (degree, NE) and, where neighbours were not gathered by label, the label.
@@ -822,11 +738,18 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
               if (slot >= a.emit_cap) continue;
               o = a.emit_rows + slot * (uint64_t)width;
             }
-            for (int j = 0; j < i; ++j) {
-              const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
-              o[kIdOrder ? j : a.L.out_col[j]] = x;
+            // the row in output-column order, two columns per 8-byte store
+            // when the row starts 8-byte aligned (global rows only)
+            auto colval = [&](int c) -> int32_t {
+              const int j = kIdOrder ? c : a.L.in_pos[c];
+              return j == i ? w : (stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j]);
+            };
+            int c = 0;
+            if (!a.staged && ((uintptr_t)o & 7) == 0) {
+              for (; c + 1 < width; c += 2)
+                *reinterpret_cast<int2 *>(o + c) = make_int2(colval(c), colval(c + 1));
             }
-            o[kIdOrder ? i : a.L.out_col[i]] = w;
+            for (; c < width; ++c) o[c] = colval(c);
           }
           if (a.staged) {
             __syncthreads();
@@ -997,28 +920,6 @@ void launch_scan(const uint32_t *W, const uint64_t *n_dev, uint64_t *S, uint64_t
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanWG), 0, s, scratch, n_dev, S, total_out);
   hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kScanWG), 0, s, W, n_dev, scratch, S);
   GSM_HIP(hipGetLastError());
-}
-
-void launch_filter_init_batch(const DeviceGraph &g, const QueryArgs *qa_dev, int nq, uint16_t *cmask,
-                              hipStream_t s) {
-  if (g.n == 0 || nq == 0) return;
-  hipLaunchKernelGGL(k_filter_init_batch, dim3(grid_for(g.n, 256, 1024), nq), dim3(256), 0, s, g, qa_dev,
-                     cmask);
-  GSM_HIP(hipGetLastError());
-}
-
-void launch_filter_refine_batch(const DeviceGraph &g, const int32_t *heavy, int64_t nheavy,
-                                const QueryArgs *qa_dev, int nq, const uint16_t *prev, uint16_t *next,
-                                hipStream_t s) {
-  if (g.n == 0 || nq == 0) return;
-  hipLaunchKernelGGL(k_refine_light_batch, dim3(grid_for(g.n * 16, 256, 2048), nq), dim3(256), 0, s, g,
-                     qa_dev, prev, next);
-  GSM_HIP(hipGetLastError());
-  if (nheavy > 0) {
-    hipLaunchKernelGGL(k_refine_heavy_batch, dim3(grid_for(nheavy * 256, 256, 1024), nq), dim3(256), 0, s,
-                       g, qa_dev, heavy, nheavy, prev, next);
-    GSM_HIP(hipGetLastError());
-  }
 }
 
 void launch_compact_first_batch(const DeviceGraph &g, const FirstBatch *fb_dev, int nq, int32_t *rows,

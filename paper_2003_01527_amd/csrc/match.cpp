@@ -238,7 +238,10 @@ struct Matcher {
     L.qbit = (uint32_t)p.order[i];
     L.next_nbr_mask = (i + 1 < p.q) ? p.backmask[i + 1] : 0;
     L.next_label = (i + 1 < p.q) ? p.qlab[p.order[i + 1]] : 0;
-    for (int j = 0; j < p.q; ++j) L.out_col[j] = p.order[j];
+    for (int j = 0; j < p.q; ++j) {
+      L.out_col[j] = p.order[j];
+      L.in_pos[p.order[j]] = j;
+    }
     return L;
   }
 
