@@ -32,6 +32,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per expansion launch from the committed rocprofv3 counter
+    record, or None when the kernels changed since it was taken."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", "k_expand_powerlaw_traffic.json")
+    src = os.path.join(ROOT, "paper_2003_01527_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.load(open(rec_path))
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("kernels_hip_sha1") == sha else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +65,8 @@ def main():
     ap.add_argument("--arrivals", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--workers", type=int, default=4, help="serving: worker streams")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON)")
+    ap.add_argument("--batch-cap-log2", type=int, default=32,
+                    help="batch: reject queries whose spanning-tree bound exceeds 2^N (20 = light mix)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (calibrates "
                          "the HBM byte counters of rocprofv3) and exit")
@@ -135,6 +151,7 @@ def main():
 
     value = tot_emb / elapsed
     achieved = (tot_bytes / 1e9) / (tot_ms / 1e3) if tot_ms > 0 else 0.0
+    traffic = measured_traffic() if args.mode == "enumerate" and not (args.wg or args.items) else None
     roofline = {
         "kernel": "k_expand (expand-verify-compact)",
         "bound": "hbm",
@@ -142,7 +159,9 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_unit": "HBM bytes per k_expand launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "alg_bytes_per_launch": tot_bytes // max(tot_launch, 1),
         "alg_bytes_per_step": tot_bytes // max(args.steps, 1),
         "kernel_ms_per_step": round(tot_ms / max(args.steps, 1), 3),
         "launches_per_step": tot_launch // max(args.steps, 1),
@@ -205,7 +224,7 @@ def bench_batch(args):
 
     from paper_2003_01527_amd import autotune
 
-    w = W.batch()
+    w = W.batch(cap=float(2 ** args.batch_cap_log2))
     torch.cuda.init()
     G = gsm.Graph.from_workload(w.graph)
     Qs = [gsm.Query.from_workload(q) for q in w.queries]
@@ -251,7 +270,8 @@ def bench_batch(args):
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": "batch: R-MAT 2^17 ef8, 16 Zipf labels; %d random-walk queries, 3-8 vertices, "
-                               "edge density 0.3-1.0; count only" % len(Qs),
+                               "edge density 0.3-1.0, spanning-tree bound <= 2^%d; count only"
+                               % (len(Qs), args.batch_cap_log2),
                    "embeddings_per_step": int(ref.sum())},
         "per_launch_queries_per_s": round(qps_p, 1),
         "autotuned": best,

@@ -283,9 +283,11 @@ def large(seed: int = 3) -> Workload:
     return Workload("large", g, [shape("K3"), shape("K4"), shape("C5"), shape("house_tail")])
 
 
-def batch(seed: int = 4, nq: int = 512, graph_seed: int = 2) -> Workload:
+def batch(seed: int = 4, nq: int = 512, graph_seed: int = 2, cap: float = CAP_DEFAULT) -> Workload:
+    """cap: spanning-tree bound above which a query is rejected (2^32 by
+    default; a small cap such as 2^20 gives a mix of light queries)."""
     g = powerlaw_graph(graph_seed)
-    qs, ex = query_set(g, nq, substream(seed, 2), k_min=3, k_max=8, dens_min=0.3, dens_max=1.0)
+    qs, ex = query_set(g, nq, substream(seed, 2), k_min=3, k_max=8, dens_min=0.3, dens_max=1.0, cap=cap)
     for i, qr in enumerate(qs):
         qr.name = "b%03d" % i
     return Workload("batch", g, qs, None, ex)
