@@ -9,7 +9,7 @@
  *   is an injective map f from the query vertices to data vertices that keeps
  *   vertex labels and maps every query edge onto a data edge (non-induced; the
  *   verification step only tests connections to already-matched vertices,
- *   Sec. 3.2 "verification").  Every such map is counted, automorphic images
+ *   Sec. 3.2, verification).  Every such map is counted, automorphic images
  *   included; rows are reported in query-vertex-id order.
  *   Method: plain depth-first backtracking (the tree-search family of Sec. 2),
  *   visiting query vertices in BFS order from vertex 0 with ascending neighbour
@@ -21,8 +21,8 @@
  *   from state x, i.e. the finaliser applied to x + 0x9E3779B97F4A7C15.
  *   Optional threads: root candidates are dealt out dynamically.
  *
- * oracle_filter — the candidate sets of the filtering stage (Sec. 3.2
- *   "filtering", Alg. 1 Filter_candidate_set): v is a candidate of query
+ * oracle_filter — the candidate sets of the filtering stage (Sec. 3.2,
+ *   filtering; Alg. 1 Filter_candidate_set): v is a candidate of query
  *   vertex u when labels are equal, deg(v) >= deg(u) and NE(v) >= NE(u), with
  *   the neighbourhood encoding NE(x) = sum over neighbours w of (label(w) + 1)
  *   (so an unlabelled graph gives NE = degree).  Each refinement round keeps
