@@ -68,6 +68,7 @@ typedef enum gsm_status {
 
 #define GSM_GRAPH_VALIDATE 1u    /* check the CSR (see gsm_graph_create) */
 #define GSM_GRAPH_DEVICE_PTRS 2u /* row_ptr, col, labels are device pointers */
+#define GSM_GRAPH_STRIP 4u       /* make the adjacency simple and undirected first */
 
 /*
  * Uploads a data graph.  The graph must be simple and undirected: each edge
@@ -80,7 +81,11 @@ typedef enum gsm_status {
  *   flags    GSM_GRAPH_VALIDATE checks every property above (O(m log d) on
  *            the host) and returns GSM_E_BAD_GRAPH on a violation;
  *            GSM_GRAPH_DEVICE_PTRS takes device pointers (copied device-side;
- *            validation then copies them to the host first).
+ *            validation then copies them to the host first);
+ *            GSM_GRAPH_STRIP accepts any adjacency with valid offsets and ids
+ *            in [0, n): self-loops are dropped, each entry v->w also adds
+ *            w->v, rows are sorted and duplicates removed, on the host, before
+ *            the upload (GSM_E_BAD_GRAPH only for bad offsets or ids).
  * Also computes per-vertex degree and neighbourhood encoding on the device.
  */
 gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col,
@@ -170,6 +175,12 @@ typedef struct gsm_match_opts {
 
 /* Write output rows straight from registers instead of staging them in LDS. */
 #define GSM_MATCH_NO_OUTPUT_STAGING 1u
+/* Leave the rows written to gsm_match's rows buffer in ascending
+ * lexicographic order (the order of the oracle's result set); with
+ * GSM_E_TRUNCATED the rows_cap rows kept are sorted among themselves.  Costs
+ * device memory beyond the frontier budget, see gsm_sort_rows.  Not valid
+ * with an emit callback (GSM_E_UNSUPPORTED). */
+#define GSM_MATCH_SORT_ROWS 2u
 
 /* Fills defaults (struct_size set, budget 0, rounds 1, degree and NE on, no slice). */
 void gsm_match_opts_init(gsm_match_opts *o);
@@ -197,6 +208,22 @@ gsm_status gsm_filter(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts,
  */
 gsm_status gsm_match(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, uint64_t *count,
                      int32_t *rows, uint64_t rows_cap, uint64_t *rows_written);
+
+/*
+ * Sorts nrows rows of q int32 ids (row-major) into ascending lexicographic
+ * order in place, on the device, on the graph's stream-ordered workspace
+ * (the embedding list of Alg. 1 output M, as a sorted set).
+ *   rows            host memory, or device memory when rows_on_device
+ *   q               1..16 columns
+ *   ids must lie in [0, n) of g; other values give an unspecified order but
+ *   never an access outside the buffers.
+ * Device memory used: 16 * ceil(q*b/64) bytes per row, b = bit width of n-1,
+ * plus 4*q bytes per row when rows are on the host; it stays with the graph
+ * for reuse.  Waits for the sort before returning.  GSM_E_OOM when the
+ * buffers cannot be allocated.
+ */
+gsm_status gsm_sort_rows(gsm_graph_t g, int32_t *rows, uint64_t nrows, int32_t q, int32_t rows_on_device,
+                         void *hip_stream);
 
 /*
  * The smallest memory_budget_bytes gsm_match accepts for qh on g: the first

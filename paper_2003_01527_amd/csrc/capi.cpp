@@ -149,6 +149,55 @@ static gsm_status validate_csr(int64_t n, const int64_t *rp, const int32_t *col)
   return GSM_OK;
 }
 
+// Simple undirected CSR from any adjacency: every entry v->w with v != w
+// becomes the edge {v, w} stored in both rows; rows are sorted and duplicate
+// entries dropped.  Offsets and ids must still be well formed.
+static gsm_status strip_csr(int64_t n, const int64_t *rp, const int32_t *col, std::vector<int64_t> &out_rp,
+                            std::vector<int32_t> &out_col) {
+  if (rp[0] != 0) {
+    gsm::set_error("row_ptr[0] != 0");
+    return GSM_E_BAD_GRAPH;
+  }
+  std::vector<int64_t> cnt((size_t)n + 1, 0);
+  for (int64_t v = 0; v < n; ++v) {
+    if (rp[v + 1] < rp[v]) {
+      gsm::set_error("row_ptr decreases at vertex " + std::to_string(v));
+      return GSM_E_BAD_GRAPH;
+    }
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k) {
+      const int32_t w = col[k];
+      if (w < 0 || w >= n) {
+        gsm::set_error("neighbour id out of range in row " + std::to_string(v));
+        return GSM_E_BAD_GRAPH;
+      }
+      if (w == v) continue;
+      cnt[v + 1]++;
+      cnt[w + 1]++;
+    }
+  }
+  for (int64_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+  std::vector<int32_t> both((size_t)cnt[n]);
+  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k) {
+      const int32_t w = col[k];
+      if (w == v) continue;
+      both[fill[v]++] = w;
+      both[fill[w]++] = (int32_t)v;
+    }
+  out_rp.assign((size_t)n + 1, 0);
+  out_col.clear();
+  out_col.reserve(both.size());
+  for (int64_t v = 0; v < n; ++v) {
+    auto b = both.begin() + cnt[v], e = both.begin() + cnt[v + 1];
+    std::sort(b, e);
+    e = std::unique(b, e);
+    out_col.insert(out_col.end(), b, e);
+    out_rp[v + 1] = (int64_t)out_col.size();
+  }
+  return GSM_OK;
+}
+
 gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col,
                             const int32_t *labels, uint32_t flags, gsm_graph_t *out) {
   GSM_API_BEGIN
@@ -172,7 +221,7 @@ gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *co
       gsm::set_error("row_ptr[n] < 0");
       return GSM_E_BAD_GRAPH;
     }
-    if ((flags & GSM_GRAPH_VALIDATE) || labels) {
+    if ((flags & (GSM_GRAPH_VALIDATE | GSM_GRAPH_STRIP)) || labels) {
       h_col_store.resize(nnz);
       if (nnz)
         GSM_HIP(hipMemcpy(h_col_store.data(), col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -189,6 +238,20 @@ gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *co
   if (nnz > 0 && !col) {
     gsm::set_error("gsm_graph_create: col is NULL");
     return GSM_E_INVALID_ARG;
+  }
+  // CSR arrays to upload: the caller's, or the cleaned host copy
+  const int64_t *src_rp = row_ptr;
+  const int32_t *src_col = col;
+  hipMemcpyKind csr_kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  std::vector<int64_t> clean_rp;
+  std::vector<int32_t> clean_col;
+  if (flags & GSM_GRAPH_STRIP) {
+    gsm_status st = strip_csr(n, h_rp, h_col, clean_rp, clean_col);
+    if (st != GSM_OK) return st;
+    h_rp = src_rp = clean_rp.data();
+    h_col = src_col = clean_col.data();
+    nnz = clean_rp[n];
+    csr_kind = hipMemcpyHostToDevice;
   }
   if (flags & GSM_GRAPH_VALIDATE) {
     gsm_status st = validate_csr(n, h_rp, h_col);
@@ -211,9 +274,9 @@ gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *co
     g->max_label = max_label;
     const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     GSM_HIP(hipMalloc((void **)&g->rp, (n + 1) * sizeof(int64_t)));
-    GSM_HIP(hipMemcpy(g->rp, row_ptr, (n + 1) * sizeof(int64_t), kind));
+    GSM_HIP(hipMemcpy(g->rp, src_rp, (n + 1) * sizeof(int64_t), csr_kind));
     GSM_HIP(hipMalloc((void **)&g->col, std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
-    if (nnz) GSM_HIP(hipMemcpy(g->col, col, nnz * sizeof(int32_t), kind));
+    if (nnz) GSM_HIP(hipMemcpy(g->col, src_col, nnz * sizeof(int32_t), csr_kind));
     GSM_HIP(hipMalloc((void **)&g->deg, std::max<int64_t>(n, 1) * sizeof(uint32_t)));
     GSM_HIP(hipMalloc((void **)&g->dne, std::max<int64_t>(n, 1) * sizeof(uint2)));
     if (labels) {

@@ -243,7 +243,18 @@ void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_
 
 // -------------------------------------------------------------- workspace --
 
+// Buffers of the device row sort.
+struct SortBuffers {
+  DevBuf keys[2], hist, offs, len, scratch;
+  DevBuf rows;  // rows copied in from host memory
+};
+
+// Sorts N rows of q int32 ids in [0, n) on the device, lexicographically
+// ascending, in place (radix sort of the rows packed into integer keys).
+void sort_rows_device(int32_t *rows, uint64_t N, int q, int64_t n, SortBuffers &sb, hipStream_t s);
+
 struct Workspace {
+  SortBuffers sort;
   DevBuf cmask, cmask2;
   DevBuf rows[kMaxQ], W[kMaxQ], apos[kMaxQ], abase[kMaxQ], S[kMaxQ];
   DevBuf qid[kMaxQ];  // batched rows: query of each row

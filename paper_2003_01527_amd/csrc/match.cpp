@@ -31,6 +31,7 @@ struct Options {
   int items = 4, wg = 512;
   bool profile = false;
   int stage_out = 1;
+  bool sort = false;
 };
 
 Options read_opts(const gsm_match_opts *o, int q) {
@@ -52,8 +53,10 @@ Options read_opts(const gsm_match_opts *o, int q) {
   if (o->tile_items) r.items = o->tile_items;
   if (o->wg_size) r.wg = o->wg_size;
   r.profile = o->profile != 0;
-  if (o->struct_size >= offsetof(gsm_match_opts, flags) + sizeof(uint32_t))
+  if (o->struct_size >= offsetof(gsm_match_opts, flags) + sizeof(uint32_t)) {
     r.stage_out = (o->flags & GSM_MATCH_NO_OUTPUT_STAGING) ? 0 : 1;
+    r.sort = (o->flags & GSM_MATCH_SORT_ROWS) != 0;
+  }
   if (r.rounds < 0 || r.rounds > 64) throw Error{GSM_E_INVALID_ARG, "filter_rounds out of [0, 64]"};
   if (r.root_q >= q) throw Error{GSM_E_INVALID_ARG, "root_qvertex >= q"};
   if (r.root_q >= 0 && r.root_mod == 0) throw Error{GSM_E_INVALID_ARG, "root_mod must be > 0"};
@@ -404,6 +407,20 @@ struct Matcher {
   }
 };
 
+// Sorts rows in host or device memory on the device and waits for it.
+void sort_rows(int32_t *rows, uint64_t N, int q, int64_t n, bool on_device, SortBuffers &sb, hipStream_t s) {
+  if (on_device) {
+    sort_rows_device(rows, N, q, n, sb, s);
+  } else {
+    const size_t bytes = sizeof(int32_t) * q * N;
+    sb.rows.reserve(bytes);
+    GSM_HIP(hipMemcpyAsync(sb.rows.ptr, rows, bytes, hipMemcpyHostToDevice, s));
+    sort_rows_device(sb.rows.as<int32_t>(), N, q, n, sb, s);
+    GSM_HIP(hipMemcpyAsync(rows, sb.rows.ptr, bytes, hipMemcpyDeviceToHost, s));
+  }
+  GSM_HIP(hipStreamSynchronize(s));
+}
+
 Workspace &acquire_ws(gsm_graph &g) {
   if (!g.ws) g.ws = new Workspace();
   return *g.ws;
@@ -474,6 +491,10 @@ gsm_status gsm_match(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, 
       return GSM_E_INVALID_ARG;
     }
     const gsm::Options o = gsm::read_opts(opts, qh->q);
+    if (o.sort && o.emit) {
+      gsm::set_error("GSM_MATCH_SORT_ROWS needs the rows buffer, not an emit callback");
+      return GSM_E_UNSUPPORTED;
+    }
     std::lock_guard<std::mutex> lk(g->mu);
     gsm::Workspace &ws = gsm::acquire_ws(*g);
     gsm::Matcher m(*g, *qh, o, ws);
@@ -486,6 +507,7 @@ gsm_status gsm_match(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, 
     m.finish_stats(c);
     *count = c;
     const uint64_t written = rows ? std::min(c, rows_cap) : 0;
+    if (o.sort && written > 1) gsm::sort_rows(rows, written, qh->q, g->n, o.rows_dev, ws.sort, m.s);
     if (rows_written) *rows_written = written;
     if (o.stats) {
       m.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -502,6 +524,31 @@ gsm_status gsm_match(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, 
       gsm::set_error("count exceeds rows_cap; first rows_cap rows written");
       return GSM_E_TRUNCATED;
     }
+    return GSM_OK;
+  } catch (const Error &e) {
+    gsm::set_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc &) {
+    gsm::set_error("host allocation failed");
+    return GSM_E_OOM;
+  }
+}
+
+gsm_status gsm_sort_rows(gsm_graph_t g, int32_t *rows, uint64_t nrows, int32_t q, int32_t rows_on_device,
+                          void *hip_stream) {
+  try {
+    if (!g || (!rows && nrows)) {
+      gsm::set_error("gsm_sort_rows: NULL argument");
+      return GSM_E_INVALID_ARG;
+    }
+    if (q < 1 || q > gsm::kMaxQ) {
+      gsm::set_error("gsm_sort_rows: q out of [1, 16]");
+      return GSM_E_INVALID_ARG;
+    }
+    if (nrows < 2) return GSM_OK;
+    std::lock_guard<std::mutex> lk(g->mu);
+    gsm::Workspace &ws = gsm::acquire_ws(*g);
+    gsm::sort_rows(rows, nrows, q, g->n, rows_on_device != 0, ws.sort, (hipStream_t)hip_stream);
     return GSM_OK;
   } catch (const Error &e) {
     gsm::set_error(e.msg);

@@ -21,6 +21,7 @@ _lib = None
 MAXQ = 16
 GRAPH_VALIDATE = 1
 GRAPH_DEVICE_PTRS = 2
+GRAPH_STRIP = 4
 
 STATUS = {0: "GSM_OK", 1: "GSM_E_INVALID_ARG", 2: "GSM_E_BAD_GRAPH", 3: "GSM_E_BAD_QUERY",
           4: "GSM_E_OOM", 5: "GSM_E_BUDGET", 6: "GSM_E_DEVICE", 7: "GSM_E_TRUNCATED",
@@ -114,6 +115,7 @@ def _load():
     lib.gsm_match.argtypes = [vp, vp, P(MatchOpts), P(u64), vp, u64, P(u64)]
     lib.gsm_match_min_budget.restype = ctypes.c_int
     lib.gsm_match_min_budget.argtypes = [vp, vp, i32, P(u64)]
+    lib.gsm_sort_rows.argtypes = [vp, vp, u64, i32, i32, vp]
     lib.gsm_server_opts_init.argtypes = [P(ServerOpts)]
     lib.gsm_server_create.restype = ctypes.c_int
     lib.gsm_server_create.argtypes = [vp, P(ServerOpts), P(vp)]
@@ -143,9 +145,9 @@ def _p(a: Optional[np.ndarray]):
 class Graph:
     """A data graph uploaded to the device (simple, undirected, sorted CSR)."""
 
-    def __init__(self, row_ptr, col, labels=None, validate: bool = False):
+    def __init__(self, row_ptr, col, labels=None, validate: bool = False, strip: bool = False):
         lib = _load()
-        flags = GRAPH_VALIDATE if validate else 0
+        flags = (GRAPH_VALIDATE if validate else 0) | (GRAPH_STRIP if strip else 0)
         self._h = ctypes.c_void_p()
         if hasattr(row_ptr, "data_ptr"):  # torch tensors on the device
             flags |= GRAPH_DEVICE_PTRS
@@ -211,9 +213,13 @@ class Query:
             pass
 
 
+FLAG_NO_OUTPUT_STAGING = 1
+FLAG_SORT_ROWS = 2
+
+
 def make_opts(budget: int = 0, filter_rounds: int = 1, use_degree: bool = True, use_ne: bool = True,
               stream=None, root=None, tile_items: int = 0, wg_size: int = 0, profile: bool = False,
-              stats: Optional[Stats] = None, stage_output: bool = True,
+              stats: Optional[Stats] = None, stage_output: bool = True, sort_rows: bool = False,
               batch_heavy_pairs: int = 0) -> MatchOpts:
     o = MatchOpts()
     _load().gsm_match_opts_init(ctypes.byref(o))
@@ -228,7 +234,7 @@ def make_opts(budget: int = 0, filter_rounds: int = 1, use_degree: bool = True, 
     o.tile_items = int(tile_items)
     o.wg_size = int(wg_size)
     o.profile = 1 if profile else 0
-    o.flags = 0 if stage_output else 1
+    o.flags = (0 if stage_output else FLAG_NO_OUTPUT_STAGING) | (FLAG_SORT_ROWS if sort_rows else 0)
     o.batch_heavy_pairs = int(batch_heavy_pairs)
     if stats is not None:
         stats.struct_size = ctypes.sizeof(Stats)
@@ -360,6 +366,28 @@ class Server:
 
 def now_ns() -> int:
     return int(_load().gsm_now_ns())
+
+
+def sort_rows(graph: Graph, rows, stream=None):
+    """Sorts rows (a numpy int32 (N, q) array, or a device torch int32 tensor
+    of that shape) lexicographically in place on the device."""
+    lib = _load()
+    if isinstance(rows, np.ndarray):
+        if rows.dtype != np.int32 or rows.ndim != 2 or not rows.flags["C_CONTIGUOUS"]:
+            raise ValueError("rows must be a C-contiguous int32 (N, q) array")
+        ptr, on_dev = _p(rows), 0
+    else:
+        if not (hasattr(rows, "is_cuda") and rows.is_cuda) or rows.dim() != 2 or not rows.is_contiguous():
+            raise ValueError("rows must be a contiguous device (N, q) tensor")
+        import torch
+        if rows.dtype != torch.int32:
+            raise ValueError("rows must be int32")
+        ptr, on_dev = ctypes.c_void_p(rows.data_ptr()), 1
+        if stream is None:
+            stream = torch.cuda.current_stream(rows.device).cuda_stream
+    st = ctypes.c_void_p(int(stream)) if stream is not None else None
+    _check(lib.gsm_sort_rows(graph._h, ptr, int(rows.shape[0]), int(rows.shape[1]), on_dev, st))
+    return rows
 
 
 def min_budget(graph: Graph, query: Query, host_rows: bool = False) -> int:
