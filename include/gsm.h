@@ -181,6 +181,12 @@ typedef struct gsm_match_opts {
  * device memory beyond the frontier budget, see gsm_sort_rows.  Not valid
  * with an emit callback (GSM_E_UNSUPPORTED). */
 #define GSM_MATCH_SORT_ROWS 2u
+/* One-step look-ahead (Sec. 3.3, k-look-ahead, k = 1) in the verification of
+ * every level that writes rows: a new row is dropped when some later query
+ * neighbour of the vertex just placed can no longer find an image among that
+ * data vertex's neighbours (too few of its label, or none that is a candidate
+ * outside the row).  Pure pruning: the result is unchanged. */
+#define GSM_MATCH_LOOKAHEAD 4u
 
 /* Fills defaults (struct_size set, budget 0, rounds 1, degree and NE on, no slice). */
 void gsm_match_opts_init(gsm_match_opts *o);

@@ -130,7 +130,19 @@ struct LevelArgs {
   int32_t next_label;      // label of position i+1
   int32_t out_col[kMaxQ];  // emit: output column (query id) of position j
   int32_t in_pos[kMaxQ];   // emit: position of output column (query id) c
+  // one-step look-ahead on a new row (0 tests = off): for each later
+  // position adjacent to position i, the new vertex needs at least la_need
+  // neighbours of that position's label, and one of them outside the row
+  // that is a candidate of it (checked when the label group has at most
+  // kLookaheadScan entries)
+  int32_t la_n;
+  int32_t la_label[kMaxQ];
+  uint32_t la_qbit[kMaxQ];
+  uint32_t la_need[kMaxQ];
 };
+
+// Longest label group of the new vertex that the look-ahead scans.
+constexpr uint32_t kLookaheadScan = 32;
 
 // --------------------------------------------------------------- kernels --
 

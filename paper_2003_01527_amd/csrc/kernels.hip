@@ -221,6 +221,32 @@ __device__ __forceinline__ uint32_t label_range(const DeviceGraph &g, int32_t x,
   return g.deg[x];
 }
 
+// One-step look-ahead (Sec. 3.3, k-look-ahead with k = 1) on a new row: the
+// ids row[0..i) already matched and w placed at position i.  Every later
+// query neighbour of position i must find its own image among w's
+// neighbours of its label: there must be at least la_need of them (those of
+// the matched neighbours included), and, for a label group short enough to
+// scan, one that is a candidate of that query vertex and not in the row.
+// Failing either, no extension of the row can be an embedding.
+__device__ __forceinline__ bool lookahead_ok(const ExpandArgs &a, int32_t w, const int32_t *row) {
+  for (int f = 0; f < a.L.la_n; ++f) {
+    int64_t base;
+    const uint32_t cnt = label_range(a.g, w, a.L.la_label[f], base);
+    if (cnt < a.L.la_need[f]) return false;
+    if (cnt > kLookaheadScan) continue;
+    bool found = false;
+    for (uint32_t t = 0; t < cnt && !found; ++t) {
+      const int32_t x = a.g.gather[base + t];
+      if (!((a.cmask[x] >> a.L.la_qbit[f]) & 1)) continue;
+      bool used = false;
+      for (int j = 0; j < a.L.i; ++j) used = used || row[j] == x;
+      found = !used;
+    }
+    if (!found) return false;
+  }
+  return true;
+}
+
 __global__ __launch_bounds__(256) void k_compact_first(DeviceGraph g, const uint16_t *cmask,
                                                        uint32_t qbit, int32_t next_label,
                                                        int32_t *rows, uint32_t *W, int64_t *abase,
@@ -606,6 +632,8 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
             keep = has_edge(a.g, x, w, probes);
           }
         }
+        if (MODE == kModeNext && keep && a.L.la_n)
+          keep = lookahead_ok(a, w, stage_in ? s_in + k * i : a.rows_in + (r0 + k) * i);
         if ((MODE == kModeNext || MODE == kModeBatch) && keep && !p_last[it]) {
           // anchor of the next position: the earlier neighbour with the fewest
           // neighbours of the next label; an empty range ends the row here

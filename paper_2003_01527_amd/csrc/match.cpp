@@ -32,6 +32,7 @@ struct Options {
   bool profile = false;
   int stage_out = 1;
   bool sort = false;
+  bool lookahead = false;
 };
 
 Options read_opts(const gsm_match_opts *o, int q) {
@@ -56,6 +57,7 @@ Options read_opts(const gsm_match_opts *o, int q) {
   if (o->struct_size >= offsetof(gsm_match_opts, flags) + sizeof(uint32_t)) {
     r.stage_out = (o->flags & GSM_MATCH_NO_OUTPUT_STAGING) ? 0 : 1;
     r.sort = (o->flags & GSM_MATCH_SORT_ROWS) != 0;
+    r.lookahead = (o->flags & GSM_MATCH_LOOKAHEAD) != 0;
   }
   if (r.rounds < 0 || r.rounds > 64) throw Error{GSM_E_INVALID_ARG, "filter_rounds out of [0, 64]"};
   if (r.root_q >= q) throw Error{GSM_E_INVALID_ARG, "root_qvertex >= q"};
@@ -244,6 +246,21 @@ struct Matcher {
     for (int j = 0; j < p.q; ++j) {
       L.out_col[j] = p.order[j];
       L.in_pos[p.order[j]] = j;
+    }
+    if (o.lookahead) {
+      // later query neighbours of the vertex placed at position i
+      const int u = p.order[i];
+      for (int k = i + 1; k < p.q; ++k) {
+        if (!((p.backmask[k] >> i) & 1)) continue;
+        const int32_t lab = p.qlab[p.order[k]];
+        uint32_t need = 0;  // neighbours of u with that label, matched or not
+        for (int v = 0; v < qh.q; ++v)
+          if (((qh.adj[u] >> v) & 1) && p.qlab[v] == lab) ++need;
+        L.la_label[L.la_n] = lab;
+        L.la_qbit[L.la_n] = (uint32_t)p.order[k];
+        L.la_need[L.la_n] = need;
+        ++L.la_n;
+      }
     }
     return L;
   }
