@@ -43,6 +43,9 @@ def _load():
         lib.oracle_match.restype = ctypes.c_int
         lib.oracle_match.argtypes = [i64, vp, vp, vp, i32, i32, vp, vp, i32, u32, u32, i32, i32,
                                      ctypes.POINTER(u64), ctypes.POINTER(vp)]
+        lib.oracle_match_ex.restype = ctypes.c_int
+        lib.oracle_match_ex.argtypes = [i64, vp, vp, vp, i32, i32, vp, vp, i32, u32, u32, i32, i32, i32,
+                                        ctypes.POINTER(u64), ctypes.POINTER(vp)]
         lib.oracle_filter.restype = ctypes.c_int
         lib.oracle_filter.argtypes = [i64, vp, vp, vp, i32, i32, vp, vp, i32, i32, i32, i32, u32, u32, vp]
         lib.oracle_triangles.restype = i64
@@ -79,12 +82,13 @@ def sort_rows(rows: np.ndarray) -> np.ndarray:
     return rows[idx]
 
 
-def match(g, qr, rows=True, threads=1, root=None):
+def match(g, qr, rows=True, threads=1, root=None, induced=False):
     """(count, rows) of all embeddings of query qr in graph g.
 
     rows are int32 (count, q) in query-vertex-id columns, sorted ascending; None
     when rows=False.  root = (query_vertex, mod, rem) restricts to embeddings
-    whose image of query_vertex lies in that slice of the slice hash.
+    whose image of query_vertex lies in that slice of the slice hash.  induced:
+    non-adjacent query vertices must map to non-adjacent data vertices too.
     """
     lib = _load()
     rp, col, lab = _graph_arrays(g)
@@ -92,8 +96,9 @@ def match(g, qr, rows=True, threads=1, root=None):
     rq, rm, rr = (-1, 0, 0) if root is None else root
     cnt = ctypes.c_uint64(0)
     out = ctypes.c_void_p()
-    rc = lib.oracle_match(g.n, _p(rp), _p(col), _p(lab), qr.q, e.shape[0], _p(e), _p(ql), rq, rm, rr,
-                          1 if rows else 0, threads, ctypes.byref(cnt), ctypes.byref(out))
+    rc = lib.oracle_match_ex(g.n, _p(rp), _p(col), _p(lab), qr.q, e.shape[0], _p(e), _p(ql), rq, rm, rr,
+                             1 if rows else 0, threads, 1 if induced else 0, ctypes.byref(cnt),
+                             ctypes.byref(out))
     if rc != 0:
         raise RuntimeError("oracle_match failed (%d)" % rc)
     count = int(cnt.value)

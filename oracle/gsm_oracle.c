@@ -20,6 +20,9 @@
  *   splitmix64 is the output of one step of Steele, Lea and Flood's generator
  *   from state x, i.e. the finaliser applied to x + 0x9E3779B97F4A7C15.
  *   Optional threads: root candidates are dealt out dynamically.
+ *   Optional induced semantics (the other common reading of subgraph
+ *   isomorphism, Sec. 1): non-adjacent query vertices must also map to
+ *   non-adjacent data vertices; every earlier non-neighbour is tested too.
  *
  * oracle_filter — the candidate sets of the filtering stage (Sec. 3.2,
  *   filtering; Alg. 1 Filter_candidate_set): v is a candidate of query
@@ -64,6 +67,8 @@ typedef struct {
   int parent[OQ_MAX];     /* query vertex whose image's neighbours are scanned */
   int nback[OQ_MAX];      /* further earlier neighbours to test, per depth */
   int back[OQ_MAX][OQ_MAX];
+  int nnon[OQ_MAX];       /* earlier non-neighbours, per depth (induced only) */
+  int non[OQ_MAX][OQ_MAX];
   int32_t label[OQ_MAX];  /* label per query vertex (0 when unlabelled) */
 } OPlan;
 
@@ -97,9 +102,11 @@ static int make_plan(int q, int ne, const int32_t *edges, const int32_t *qlab, O
   for (int k = 0; k < q; ++k) {
     int u = p->order[k];
     p->nback[k] = 0;
+    p->nnon[k] = 0;
     for (int j = 0; j < k; ++j) {
       int w = p->order[j];
       if (A[u][w] && w != p->parent[k]) p->back[k][p->nback[k]++] = w;
+      if (!A[u][w]) p->non[k][p->nnon[k]++] = w;
     }
   }
   return 0;
@@ -114,6 +121,7 @@ typedef struct {
   int root_q;
   uint32_t root_mod, root_rem;
   int want_rows;
+  int induced;
   /* shared root dispenser */
   int64_t next_root;
   pthread_mutex_t mu;
@@ -157,6 +165,9 @@ static int admissible(Worker *w, int k, int32_t v) {
     return 0;
   for (int b = 0; b < p->nback[k]; ++b)
     if (!has_edge(s->rp, s->col, w->f[p->back[k][b]], v)) return 0;
+  if (s->induced)
+    for (int b = 0; b < p->nnon[k]; ++b)
+      if (has_edge(s->rp, s->col, w->f[p->non[k][b]], v)) return 0;
   return 1;
 }
 
@@ -208,10 +219,10 @@ static void *worker_main(void *arg) {
  * malloc'd array of count*q int32 (query-id columns, unsorted; release with
  * oracle_free).  nthreads <= 1 runs on the calling thread only.
  */
-int oracle_match(int64_t n, const int64_t *rp, const int32_t *col, const int32_t *lab, int32_t q,
-                 int32_t ne, const int32_t *edges, const int32_t *qlab, int32_t root_q,
-                 uint32_t root_mod, uint32_t root_rem, int32_t want_rows, int32_t nthreads,
-                 uint64_t *count, int32_t **rows_out) {
+int oracle_match_ex(int64_t n, const int64_t *rp, const int32_t *col, const int32_t *lab, int32_t q,
+                    int32_t ne, const int32_t *edges, const int32_t *qlab, int32_t root_q,
+                    uint32_t root_mod, uint32_t root_rem, int32_t want_rows, int32_t nthreads,
+                    int32_t induced, uint64_t *count, int32_t **rows_out) {
   OPlan p;
   if (q < 1 || q > OQ_MAX || make_plan(q, ne, edges, qlab, &p) != 0) return -1;
   Shared s;
@@ -224,6 +235,7 @@ int oracle_match(int64_t n, const int64_t *rp, const int32_t *col, const int32_t
   s.root_mod = root_mod;
   s.root_rem = root_rem;
   s.want_rows = want_rows;
+  s.induced = induced != 0;
   s.next_root = 0;
   pthread_mutex_init(&s.mu, NULL);
   if (nthreads < 1) nthreads = 1;
@@ -273,6 +285,15 @@ int oracle_match(int64_t n, const int64_t *rp, const int32_t *col, const int32_t
   pthread_mutex_destroy(&s.mu);
   if (rc == 0) *count = total;
   return rc;
+}
+
+/* oracle_match_ex with non-induced semantics. */
+int oracle_match(int64_t n, const int64_t *rp, const int32_t *col, const int32_t *lab, int32_t q,
+                 int32_t ne, const int32_t *edges, const int32_t *qlab, int32_t root_q,
+                 uint32_t root_mod, uint32_t root_rem, int32_t want_rows, int32_t nthreads,
+                 uint64_t *count, int32_t **rows_out) {
+  return oracle_match_ex(n, rp, col, lab, q, ne, edges, qlab, root_q, root_mod, root_rem, want_rows, nthreads, 0,
+                         count, rows_out);
 }
 
 void oracle_free(void *p) { free(p); }
