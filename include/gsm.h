@@ -109,6 +109,19 @@ gsm_status gsm_query_create(int32_t q, int32_t ne, const int32_t *edges, const i
 void gsm_query_destroy(gsm_query_t qh);
 
 /*
+ * Symmetry of a query (host only, computed at gsm_query_create): aut gets
+ * |Aut(Q)|, the number of automorphisms (label- and edge-preserving
+ * permutations of the query vertices); pairs gets up to pairs_cap constraints
+ * as (a, b) query-id pairs meaning f(a) < f(b), npairs their number (at most
+ * q*(q-1)/2).  Stabilizer chain: the smallest vertex with a non-trivial orbit
+ * under the automorphisms fixing the vertices chosen before is required below
+ * every other vertex of its orbit, then fixed.  Any pointer may be NULL when
+ * its cap is 0.
+ */
+gsm_status gsm_query_symmetry(gsm_query_t qh, uint64_t *aut, int32_t *pairs, int32_t pairs_cap,
+                              int32_t *npairs);
+
+/*
  * The host pre-computation of Alg. 1 (PreCompute_on_CPUs, Sec. 3.2): query
  * vertices in visiting order, greedily by larger d_M (edges to vertices
  * already ordered), smaller P_f (label frequency times the fraction of data
@@ -187,6 +200,14 @@ typedef struct gsm_match_opts {
  * data vertex's neighbours (too few of its label, or none that is a candidate
  * outside the row).  Pure pruning: the result is unchanged. */
 #define GSM_MATCH_LOOKAHEAD 4u
+/* Unique-subgraph mode: one embedding per subgraph of the data graph that
+ * the query maps onto (the paper's way of producing each node combination
+ * once by visiting equivalent query nodes in increasing id order, Sec. 3.3).
+ * Embeddings f and f o s, s an automorphism of the query, are one subgraph;
+ * the one kept satisfies the ordering constraints that gsm_query_symmetry
+ * returns.  count = (count without the flag) / |Aut(Q)|.  Single-query
+ * matching only (gsm_match_batch returns GSM_E_UNSUPPORTED). */
+#define GSM_MATCH_UNIQUE 8u
 
 /* Fills defaults (struct_size set, budget 0, rounds 1, degree and NE on, no slice). */
 void gsm_match_opts_init(gsm_match_opts *o);

@@ -198,6 +198,24 @@ static gsm_status strip_csr(int64_t n, const int64_t *rp, const int32_t *col, st
   return GSM_OK;
 }
 
+gsm_status gsm_query_symmetry(gsm_query_t qh, uint64_t *aut, int32_t *pairs, int32_t pairs_cap,
+                              int32_t *npairs) {
+  GSM_API_BEGIN
+  if (!qh || (pairs_cap > 0 && !pairs)) {
+    gsm::set_error("gsm_query_symmetry: NULL argument");
+    return GSM_E_INVALID_ARG;
+  }
+  const int32_t n = (int32_t)(qh->sym_pairs.size() / 2);
+  if (aut) *aut = qh->aut;
+  if (npairs) *npairs = n;
+  for (int32_t k = 0; k < n && k < pairs_cap; ++k) {
+    pairs[2 * k] = qh->sym_pairs[2 * k];
+    pairs[2 * k + 1] = qh->sym_pairs[2 * k + 1];
+  }
+  return GSM_OK;
+  GSM_API_END
+}
+
 gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col,
                             const int32_t *labels, uint32_t flags, gsm_graph_t *out) {
   GSM_API_BEGIN
@@ -391,6 +409,7 @@ gsm_status gsm_query_create(int32_t q, int32_t ne, const int32_t *edges, const i
     gsm::set_error("query graph is not connected");
     return GSM_E_BAD_QUERY;
   }
+  gsm::compute_symmetry(*qh);
   *out = qh.release();
   return GSM_OK;
   GSM_API_END

@@ -86,6 +86,9 @@ struct gsm_query {
   std::vector<int32_t> edges;  // 2*ne
   int32_t label[gsm::kMaxQ] = {0};
   uint32_t adj[gsm::kMaxQ] = {0};  // adjacency bitmask by query id
+  // symmetry: |Aut(Q)| and constraints f(sym_pairs[2k]) < f(sym_pairs[2k+1])
+  uint64_t aut = 1;
+  std::vector<int32_t> sym_pairs;
 };
 
 namespace gsm {
@@ -108,6 +111,9 @@ struct Plan {
 };
 
 Plan make_plan(const gsm_graph &g, const gsm_query &q);
+
+// Fills q.aut and q.sym_pairs (unique-subgraph mode).
+void compute_symmetry(gsm_query &q);
 
 // Query description handed to kernels by value.
 struct QueryArgs {
@@ -135,6 +141,9 @@ struct LevelArgs {
   // neighbours of that position's label, and one of them outside the row
   // that is a candidate of it (checked when the label group has at most
   // kLookaheadScan entries)
+  // unique-subgraph mode: positions j < i whose id must be below (sym_lt)
+  // or above (sym_gt) the new vertex's id
+  uint32_t sym_lt, sym_gt;
   int32_t la_n;
   int32_t la_label[kMaxQ];
   uint32_t la_qbit[kMaxQ];

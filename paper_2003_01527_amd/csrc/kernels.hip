@@ -65,18 +65,20 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *sw, ui
 
 __device__ __forceinline__ bool has_edge(const DeviceGraph &g, int32_t x, int32_t w,
                                          uint32_t &probes) {
-  int64_t lo = g.rp[x];
-  const int64_t end = g.rp[x + 1];
-  int64_t hi = end;
-  while (lo < hi) {
-    ++probes;
-    int64_t mid = (lo + hi) >> 1;
-    if (g.col[mid] < w)
-      lo = mid + 1;
-    else
-      hi = mid;
+  // N(x) is sorted: halve the window [0, n) to the last entry <= w, 32-bit
+  // offsets from the row start
+  const int64_t b = g.rp[x];
+  const int32_t *c = g.col + b;
+  uint32_t n = (uint32_t)(g.rp[x + 1] - b);
+  if (n == 0) return false;
+  uint32_t lo = 0;
+  probes += n > 1 ? 33 - __builtin_clz(n - 1) : 1;  // halving steps + final compare
+  while (n > 1) {
+    const uint32_t half = n >> 1;
+    lo = (c[lo + half] <= w) ? lo + half : lo;
+    n -= half;
   }
-  return lo < end && g.col[lo] == w;
+  return c[lo] == w;
 }
 
 // ------------------------------------------------------------ graph stats --
@@ -624,6 +626,12 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
           const int j = __builtin_ctz(m);
           const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
           keep = keep && (x != w);
+        }
+        // unique-subgraph mode: id order against symmetric earlier positions
+        for (uint32_t m = a.L.sym_lt | a.L.sym_gt; m; m &= m - 1) {
+          const int j = __builtin_ctz(m);
+          const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
+          keep = keep && (((a.L.sym_lt >> j) & 1) ? x < w : x > w);
         }
         for (uint32_t m = p_nbr[it]; m; m &= m - 1) {
           const int j = __builtin_ctz(m);

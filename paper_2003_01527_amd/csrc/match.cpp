@@ -33,6 +33,7 @@ struct Options {
   int stage_out = 1;
   bool sort = false;
   bool lookahead = false;
+  bool unique = false;
 };
 
 Options read_opts(const gsm_match_opts *o, int q) {
@@ -58,6 +59,7 @@ Options read_opts(const gsm_match_opts *o, int q) {
     r.stage_out = (o->flags & GSM_MATCH_NO_OUTPUT_STAGING) ? 0 : 1;
     r.sort = (o->flags & GSM_MATCH_SORT_ROWS) != 0;
     r.lookahead = (o->flags & GSM_MATCH_LOOKAHEAD) != 0;
+    r.unique = (o->flags & GSM_MATCH_UNIQUE) != 0;
   }
   if (r.rounds < 0 || r.rounds > 64) throw Error{GSM_E_INVALID_ARG, "filter_rounds out of [0, 64]"};
   if (r.root_q >= q) throw Error{GSM_E_INVALID_ARG, "root_qvertex >= q"};
@@ -246,6 +248,14 @@ struct Matcher {
     for (int j = 0; j < p.q; ++j) {
       L.out_col[j] = p.order[j];
       L.in_pos[p.order[j]] = j;
+    }
+    if (o.unique) {
+      // symmetry-breaking constraints whose later vertex is placed at position i
+      for (size_t k = 0; k + 1 < qh.sym_pairs.size(); k += 2) {
+        const int pa = p.pos[qh.sym_pairs[k]], pb = p.pos[qh.sym_pairs[k + 1]];
+        if (pb == i && pa < i) L.sym_lt |= 1u << pa;  // f(a) < f(b) = w
+        if (pa == i && pb < i) L.sym_gt |= 1u << pb;  // w = f(a) < f(b)
+      }
     }
     if (o.lookahead) {
       // later query neighbours of the vertex placed at position i

@@ -116,6 +116,7 @@ def _load():
     lib.gsm_match_min_budget.restype = ctypes.c_int
     lib.gsm_match_min_budget.argtypes = [vp, vp, i32, P(u64)]
     lib.gsm_sort_rows.argtypes = [vp, vp, u64, i32, i32, vp]
+    lib.gsm_query_symmetry.argtypes = [vp, P(u64), vp, i32, P(i32)]
     lib.gsm_server_opts_init.argtypes = [P(ServerOpts)]
     lib.gsm_server_create.restype = ctypes.c_int
     lib.gsm_server_create.argtypes = [vp, P(ServerOpts), P(vp)]
@@ -216,12 +217,13 @@ class Query:
 FLAG_NO_OUTPUT_STAGING = 1
 FLAG_SORT_ROWS = 2
 FLAG_LOOKAHEAD = 4
+FLAG_UNIQUE = 8
 
 
 def make_opts(budget: int = 0, filter_rounds: int = 1, use_degree: bool = True, use_ne: bool = True,
               stream=None, root=None, tile_items: int = 0, wg_size: int = 0, profile: bool = False,
               stats: Optional[Stats] = None, stage_output: bool = True, sort_rows: bool = False,
-              lookahead: bool = False, batch_heavy_pairs: int = 0) -> MatchOpts:
+              lookahead: bool = False, unique: bool = False, batch_heavy_pairs: int = 0) -> MatchOpts:
     o = MatchOpts()
     _load().gsm_match_opts_init(ctypes.byref(o))
     o.memory_budget_bytes = int(budget)
@@ -236,7 +238,7 @@ def make_opts(budget: int = 0, filter_rounds: int = 1, use_degree: bool = True, 
     o.wg_size = int(wg_size)
     o.profile = 1 if profile else 0
     o.flags = ((0 if stage_output else FLAG_NO_OUTPUT_STAGING) | (FLAG_SORT_ROWS if sort_rows else 0)
-               | (FLAG_LOOKAHEAD if lookahead else 0))
+               | (FLAG_LOOKAHEAD if lookahead else 0) | (FLAG_UNIQUE if unique else 0))
     o.batch_heavy_pairs = int(batch_heavy_pairs)
     if stats is not None:
         stats.struct_size = ctypes.sizeof(Stats)
@@ -368,6 +370,15 @@ class Server:
 
 def now_ns() -> int:
     return int(_load().gsm_now_ns())
+
+
+def symmetry(query: Query):
+    """(|Aut(Q)|, [(a, b), ...]) with constraints f(a) < f(b) of the unique mode."""
+    lib = _load()
+    aut, n = ctypes.c_uint64(0), ctypes.c_int32(0)
+    buf = np.zeros(2 * 16 * 16, dtype=np.int32)
+    _check(lib.gsm_query_symmetry(query._h, ctypes.byref(aut), _p(buf), 16 * 16, ctypes.byref(n)))
+    return int(aut.value), [(int(buf[2 * k]), int(buf[2 * k + 1])) for k in range(n.value)]
 
 
 def sort_rows(graph: Graph, rows, stream=None):
