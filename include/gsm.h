@@ -208,6 +208,12 @@ typedef struct gsm_match_opts {
  * returns.  count = (count without the flag) / |Aut(Q)|.  Single-query
  * matching only (gsm_match_batch returns GSM_E_UNSUPPORTED). */
 #define GSM_MATCH_UNIQUE 8u
+/* Induced semantics (the other reading of subgraph isomorphism, Sec. 1):
+ * query vertices that are not adjacent must map to data vertices that are
+ * not adjacent either.  Every earlier non-neighbour of a new query vertex
+ * costs one more membership search per surviving pair.  Combines with the
+ * other flags; single-query matching only. */
+#define GSM_MATCH_INDUCED 16u
 
 /* Fills defaults (struct_size set, budget 0, rounds 1, degree and NE on, no slice). */
 void gsm_match_opts_init(gsm_match_opts *o);

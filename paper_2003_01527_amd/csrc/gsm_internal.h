@@ -144,6 +144,9 @@ struct LevelArgs {
   // unique-subgraph mode: positions j < i whose id must be below (sym_lt)
   // or above (sym_gt) the new vertex's id
   uint32_t sym_lt, sym_gt;
+  // induced mode: positions j < i not adjacent to position i, whose ids must
+  // not be neighbours of the new vertex
+  uint32_t non_mask;
   int32_t la_n;
   int32_t la_label[kMaxQ];
   uint32_t la_qbit[kMaxQ];

@@ -640,6 +640,14 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
             keep = has_edge(a.g, x, w, probes);
           }
         }
+        // induced mode: no edge to the earlier non-neighbours either
+        for (uint32_t m = a.L.non_mask; m; m &= m - 1) {
+          const int j = __builtin_ctz(m);
+          if (keep) {
+            const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
+            keep = !has_edge(a.g, x, w, probes);
+          }
+        }
         if (MODE == kModeNext && keep && a.L.la_n)
           keep = lookahead_ok(a, w, stage_in ? s_in + k * i : a.rows_in + (r0 + k) * i);
         if ((MODE == kModeNext || MODE == kModeBatch) && keep && !p_last[it]) {

@@ -34,6 +34,7 @@ struct Options {
   bool sort = false;
   bool lookahead = false;
   bool unique = false;
+  bool induced = false;
 };
 
 Options read_opts(const gsm_match_opts *o, int q) {
@@ -60,6 +61,7 @@ Options read_opts(const gsm_match_opts *o, int q) {
     r.sort = (o->flags & GSM_MATCH_SORT_ROWS) != 0;
     r.lookahead = (o->flags & GSM_MATCH_LOOKAHEAD) != 0;
     r.unique = (o->flags & GSM_MATCH_UNIQUE) != 0;
+    r.induced = (o->flags & GSM_MATCH_INDUCED) != 0;
   }
   if (r.rounds < 0 || r.rounds > 64) throw Error{GSM_E_INVALID_ARG, "filter_rounds out of [0, 64]"};
   if (r.root_q >= q) throw Error{GSM_E_INVALID_ARG, "root_qvertex >= q"};
@@ -249,6 +251,7 @@ struct Matcher {
       L.out_col[j] = p.order[j];
       L.in_pos[p.order[j]] = j;
     }
+    if (o.induced) L.non_mask = ((1u << i) - 1u) & ~p.backmask[i];
     if (o.unique) {
       // symmetry-breaking constraints whose later vertex is placed at position i
       for (size_t k = 0; k + 1 < qh.sym_pairs.size(); k += 2) {
