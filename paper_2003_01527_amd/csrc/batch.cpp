@@ -41,6 +41,13 @@ struct BatchMatcher {
   uint64_t launches = 0;
   uint64_t level_pairs[kMaxQ] = {0};
   uint64_t level_rows[kMaxQ] = {0};
+  // a query whose (row, neighbour) pairs at some level exceed evict_pairs
+  // leaves the shared launches (its rows expand to nothing from then on) and
+  // is matched alone afterwards: a query-uniform launch is cheaper per pair
+  uint64_t evict_pairs = 0;  // 0 = never
+  std::vector<uint8_t> evicted;
+  std::vector<uint64_t> h_qpairs;
+  bool any_evicted = false;
 
   BatchMatcher(gsm_graph &g_, const gsm_query *const *q_, int nq_, Workspace &ws_, hipStream_t s_)
       : g(g_), qs(q_, q_ + nq_), ws(ws_), s(s_), nq(nq_) {
@@ -60,8 +67,17 @@ struct BatchMatcher {
     sync();
   }
 
+  // query slot nq: rows of evicted queries are retagged to it; every
+  // candidate test fails there (no vertex has 2^32 - 1 neighbours)
   void upload_tables() {
-    std::vector<BatchLevel> bl((size_t)nq * kMaxQ);
+    std::vector<BatchLevel> bl((size_t)(nq + 1) * kMaxQ);
+    for (int i = 0; i < kMaxQ; ++i) {
+      BatchLevel &e = bl[(size_t)nq * kMaxQ + i];
+      std::memset(&e, 0, sizeof(e));
+      e.qdeg = 0xffffffffu;
+      e.qne = 0xffffffffull;
+      e.qlab = -1;
+    }
     std::vector<FirstBatch> fb(nq);
     for (int k = 0; k < nq; ++k) {
       const Plan &p = plans[k];
@@ -92,9 +108,9 @@ struct BatchMatcher {
     GSM_HIP(hipMemcpyAsync(base + o_fb, fb.data(), b_fb, hipMemcpyHostToDevice, s));
     d_bl = reinterpret_cast<BatchLevel *>(base);
     d_fb = reinterpret_cast<FirstBatch *>(base + o_fb);
-    ws.counts.reserve(std::max(nq, 1) * sizeof(uint64_t));
+    ws.counts.reserve((nq + 1) * sizeof(uint64_t));
     d_counts = ws.counts.as<uint64_t>();
-    GSM_HIP(hipMemsetAsync(d_counts, 0, std::max(nq, 1) * sizeof(uint64_t), s));
+    GSM_HIP(hipMemsetAsync(d_counts, 0, (nq + 1) * sizeof(uint64_t), s));
   }
 
   void plan_capacity() {
@@ -143,7 +159,37 @@ struct BatchMatcher {
     ws.S[i].reserve((rows + 1) * 8);
   }
 
+  void evict_heavy(int i) {
+    if (evict_pairs) {
+      ws.qpairs.reserve((nq + 1) * sizeof(uint64_t));
+      ws.evicted.reserve(nq + 1);
+      h_qpairs.resize(nq + 1);
+      if (evicted.size() != (size_t)nq + 1) evicted.assign(nq + 1, 0);
+      GSM_HIP(hipMemsetAsync(ws.qpairs.ptr, 0, (nq + 1) * sizeof(uint64_t), s));
+      launch_query_pairs(ws.W[i].as<uint32_t>(), ws.qid[i].as<uint16_t>(), dcnt + kCntRows + i, cap[i],
+                         ws.qpairs.as<uint64_t>(), s);
+      GSM_HIP(hipMemcpyAsync(h_qpairs.data(), ws.qpairs.ptr, (nq + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                             s));
+      sync();
+      bool newly = false;
+      for (int k = 0; k < nq; ++k)
+        if (!evicted[k] && h_qpairs[k] > evict_pairs) {
+          evicted[k] = 1;
+          newly = true;
+        }
+      if (newly) {
+        GSM_HIP(hipMemcpyAsync(ws.evicted.ptr, evicted.data(), nq + 1, hipMemcpyHostToDevice, s));
+        sync();
+        any_evicted = true;
+      }
+    }
+    if (any_evicted)
+      launch_retire_evicted(ws.W[i].as<uint32_t>(), ws.qid[i].as<uint16_t>(), dcnt + kCntRows + i, cap[i],
+                            ws.evicted.as<uint8_t>(), (uint16_t)nq, s);
+  }
+
   void process_level(int i) {
+    evict_heavy(i);
     launch_scan(ws.W[i].as<uint32_t>(), dcnt + kCntRows + i, ws.S[i].as<uint64_t>(), dcnt + kCntPairs + i,
                 ws.scan_scratch.as<uint64_t>(), s);
     fetch_counters();
@@ -229,6 +275,7 @@ void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_
       m.items = o.tile_items ? o.tile_items : 4;
       m.budget = o.memory_budget_bytes ? o.memory_budget_bytes : (uint64_t(4) << 30);
     };
+    const uint64_t heavy_pairs_opt = o.batch_heavy_pairs ? o.batch_heavy_pairs : (uint64_t(1) << 18);
     // split: heavy queries on launches of their own, the rest shared
     const uint64_t heavy_pairs = o.batch_heavy_pairs ? o.batch_heavy_pairs : (uint64_t(1) << 18);
     std::vector<int> light;
@@ -253,6 +300,7 @@ void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_
       std::vector<uint64_t> c(grp.size());
       BatchMatcher m(g, sub.data(), (int)sub.size(), ws, stream);
       configure(m);
+      m.evict_pairs = heavy_pairs_opt == UINT64_MAX ? 0 : heavy_pairs_opt;
       m.plan_capacity();
       m.run(c.data());
       launches += m.launches;
@@ -261,7 +309,8 @@ void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_
           st->pairs[i] += m.level_pairs[i];
           if (i > 0) st->rows[i - 1] += m.level_rows[i];
         }
-      for (size_t j = 0; j < grp.size(); ++j) counts[grp[j]] = c[j];
+      for (size_t j = 0; j < grp.size(); ++j)
+        counts[grp[j]] = (j < m.evicted.size() && m.evicted[j]) ? match_count_one(g, *qs[grp[j]], o, ws) : c[j];
     }
     if (launches_out) *launches_out = launches;
 }

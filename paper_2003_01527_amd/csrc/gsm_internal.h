@@ -243,6 +243,15 @@ struct ExpandArgs {
 
 void launch_expand(const ExpandArgs &a, int mode, int wg, int items, hipStream_t s);
 
+// Batched helpers: qpairs[q] += W[r] over the *n_dev rows r of query qid[r];
+// rows whose query is marked in evicted get W = 1 and qid = retired (a query
+// slot whose candidate test fails).  rows_hint bounds *n_dev (it only sizes
+// the grid).
+void launch_query_pairs(const uint32_t *W, const uint16_t *qid, const uint64_t *n_dev, uint64_t rows_hint,
+                        uint64_t *qpairs, hipStream_t s);
+void launch_retire_evicted(uint32_t *W, uint16_t *qid, const uint64_t *n_dev, uint64_t rows_hint,
+                           const uint8_t *evicted, uint16_t retired, hipStream_t s);
+
 // First frontier of every query: rows tagged with the query id; queries with a
 // single vertex are counted into counts[k] directly.
 struct FirstBatch {
@@ -284,6 +293,8 @@ struct Workspace {
   DevBuf qid[kMaxQ];  // batched rows: query of each row
   DevBuf tables;      // batched per-query parameter tables
   DevBuf counts;      // batched per-query counts
+  DevBuf qpairs;      // batched per-query pairs of one level
+  DevBuf evicted;     // batched: queries taken out of the shared launches
   DevBuf counters;  // kMaxQ + 8 uint64
   DevBuf scan_scratch;
   DevBuf emit;      // staging for host-bound rows

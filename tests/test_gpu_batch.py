@@ -42,6 +42,9 @@ def test_batch_random_instances(seed):
     assert gsm.match_batch(G, Qs, filter_rounds=seed % 3).tolist() == expect
     assert gsm.match_batch(G, Qs, batch_heavy_pairs=2 ** 64 - 1).tolist() == expect
     assert gsm.match_batch(G, Qs, batch_heavy_pairs=1).tolist() == expect
+    # small thresholds: queries leave the shared launches at deeper levels
+    for heavy in (4, 16, 64):
+        assert gsm.match_batch(G, Qs, batch_heavy_pairs=heavy).tolist() == expect, heavy
 
 
 @pytest.fixture(scope="module")
@@ -53,9 +56,10 @@ def batch_workload():
     return w, G, Qs, per
 
 
-@pytest.mark.parametrize("heavy", [0, 1, 2 ** 64 - 1])
+@pytest.mark.parametrize("heavy", [0, 1, 2 ** 12, 2 ** 16, 2 ** 20, 2 ** 64 - 1])
 def test_batch_equals_per_query_on_batch_workload(batch_workload, heavy):
-    """Default split, every query on its own launches, every query shared."""
+    """Default split, every query on its own launches, every query shared, and
+    thresholds that take queries out of the shared launches at deeper levels."""
     w, G, Qs, per = batch_workload
     got = gsm.match_batch(G, Qs, budget=64 << 30, batch_heavy_pairs=heavy)
     np.testing.assert_array_equal(got, per)
@@ -65,6 +69,8 @@ def test_batch_chunked_by_small_budget(batch_workload):
     w, G, Qs, per = batch_workload
     sub = list(range(0, 512, 8))
     got = gsm.match_batch(G, [Qs[k] for k in sub], budget=600 << 20)
+    np.testing.assert_array_equal(got, per[sub])
+    got = gsm.match_batch(G, [Qs[k] for k in sub], budget=600 << 20, batch_heavy_pairs=2 ** 14)
     np.testing.assert_array_equal(got, per[sub])
 
 
