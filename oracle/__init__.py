@@ -53,6 +53,9 @@ def _load():
         lib.oracle_slice_hash.restype = u64
         lib.oracle_slice_hash.argtypes = [u64]
         lib.oracle_free.argtypes = [vp]
+        lib.oracle_match_el.restype = ctypes.c_int
+        lib.oracle_match_el.argtypes = [i64, vp, vp, vp, vp, i32, i32, vp, vp, vp, i32, u32, u32, i32, i32, i32,
+                                        ctypes.POINTER(u64), ctypes.POINTER(vp)]
         _lib = lib
     return _lib
 
@@ -66,6 +69,11 @@ def _graph_arrays(g):
     col = np.ascontiguousarray(g.col, dtype=np.int32)
     lab = None if g.labels is None else np.ascontiguousarray(g.labels, dtype=np.int32)
     return rp, col, lab
+
+
+def _edge_labels(x):
+    el = getattr(x, "edge_labels", None)
+    return None if el is None else np.ascontiguousarray(el, dtype=np.int32)
 
 
 def _query_arrays(qr):
@@ -89,6 +97,8 @@ def match(g, qr, rows=True, threads=1, root=None, induced=False):
     when rows=False.  root = (query_vertex, mod, rem) restricts to embeddings
     whose image of query_vertex lies in that slice of the slice hash.  induced:
     non-adjacent query vertices must map to non-adjacent data vertices too.
+    Edge labels are taken from g.edge_labels (per CSR entry) and
+    qr.edge_labels (per query edge) when present.
     """
     lib = _load()
     rp, col, lab = _graph_arrays(g)
@@ -96,8 +106,9 @@ def match(g, qr, rows=True, threads=1, root=None, induced=False):
     rq, rm, rr = (-1, 0, 0) if root is None else root
     cnt = ctypes.c_uint64(0)
     out = ctypes.c_void_p()
-    rc = lib.oracle_match_ex(g.n, _p(rp), _p(col), _p(lab), qr.q, e.shape[0], _p(e), _p(ql), rq, rm, rr,
-                             1 if rows else 0, threads, 1 if induced else 0, ctypes.byref(cnt),
+    gel, qel = _edge_labels(g), _edge_labels(qr)
+    rc = lib.oracle_match_el(g.n, _p(rp), _p(col), _p(lab), _p(gel), qr.q, e.shape[0], _p(e), _p(ql), _p(qel),
+                             rq, rm, rr, 1 if rows else 0, threads, 1 if induced else 0, ctypes.byref(cnt),
                              ctypes.byref(out))
     if rc != 0:
         raise RuntimeError("oracle_match failed (%d)" % rc)

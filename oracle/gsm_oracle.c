@@ -23,6 +23,11 @@
  *   Optional induced semantics (the other common reading of subgraph
  *   isomorphism, Sec. 1): non-adjacent query vertices must also map to
  *   non-adjacent data vertices; every earlier non-neighbour is tested too.
+ *   Optional edge labels (the labelled graphs of Sec. 3.1 carry node and edge
+ *   labels): every query edge {a, b} must map onto a data edge with the same
+ *   label.  Graph edge labels are given per CSR entry (both directions of an
+ *   edge carry its label; none given = every edge has label 0); query edge
+ *   labels per query edge (none given = no edge-label constraint).
  *
  * oracle_filter — the candidate sets of the filtering stage (Sec. 3.2,
  *   filtering; Alg. 1 Filter_candidate_set): v is a candidate of query
@@ -49,6 +54,19 @@ static uint64_t slice_hash(uint64_t x) {
 
 uint64_t oracle_slice_hash(uint64_t x) { return slice_hash(x); }
 
+/* CSR position of b in the row of a, or -1. */
+static int64_t edge_pos(const int64_t *rp, const int32_t *col, int32_t a, int32_t b) {
+  int64_t lo = rp[a], hi = rp[a + 1];
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (col[mid] < b)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < rp[a + 1] && col[lo] == b) ? lo : -1;
+}
+
 static int has_edge(const int64_t *rp, const int32_t *col, int32_t a, int32_t b) {
   int64_t lo = rp[a], hi = rp[a + 1];
   while (lo < hi) {
@@ -70,16 +88,20 @@ typedef struct {
   int nnon[OQ_MAX];       /* earlier non-neighbours, per depth (induced only) */
   int non[OQ_MAX][OQ_MAX];
   int32_t label[OQ_MAX];  /* label per query vertex (0 when unlabelled) */
+  int has_elab;           /* query edge labels given */
+  int32_t elab[OQ_MAX][OQ_MAX]; /* label of query edge {a, b} */
 } OPlan;
 
 /* BFS order from query vertex 0, neighbours in ascending id.  -1 if not connected. */
-static int make_plan(int q, int ne, const int32_t *edges, const int32_t *qlab, OPlan *p) {
+static int make_plan(int q, int ne, const int32_t *edges, const int32_t *qlab, const int32_t *qelab, OPlan *p) {
   int A[OQ_MAX][OQ_MAX];
   memset(A, 0, sizeof(A));
+  p->has_elab = qelab != NULL;
   for (int e = 0; e < ne; ++e) {
     int a = edges[2 * e], b = edges[2 * e + 1];
     if (a < 0 || b < 0 || a >= q || b >= q || a == b) return -1;
     A[a][b] = A[b][a] = 1;
+    if (qelab) p->elab[a][b] = p->elab[b][a] = qelab[e];
   }
   p->q = q;
   for (int u = 0; u < q; ++u) p->label[u] = qlab ? qlab[u] : 0;
@@ -117,6 +139,7 @@ typedef struct {
   const int64_t *rp;
   const int32_t *col;
   const int32_t *lab;
+  const int32_t *elab;  /* per CSR entry, or NULL */
   const OPlan *p;
   int root_q;
   uint32_t root_mod, root_rem;
@@ -155,7 +178,12 @@ static void emit(Worker *w) {
   w->nrows++;
 }
 
-static int admissible(Worker *w, int k, int32_t v) {
+/* Label of the data edge at CSR position e (0 when the graph has none). */
+static int32_t data_elab(const Shared *s, int64_t e) { return s->elab ? s->elab[e] : 0; }
+
+/* v for query vertex order[k]; e = CSR position of v in its parent image's
+ * row (-1 at depth 0). */
+static int admissible(Worker *w, int k, int32_t v, int64_t e) {
   Shared *s = w->s;
   const OPlan *p = s->p;
   int u = p->order[k];
@@ -163,8 +191,16 @@ static int admissible(Worker *w, int k, int32_t v) {
   if (w->used[v]) return 0;
   if (u == s->root_q && s->root_mod > 0 && slice_hash((uint64_t)v) % s->root_mod != s->root_rem)
     return 0;
-  for (int b = 0; b < p->nback[k]; ++b)
-    if (!has_edge(s->rp, s->col, w->f[p->back[k][b]], v)) return 0;
+  if (p->has_elab && e >= 0 && data_elab(s, e) != p->elab[p->parent[k]][u]) return 0;
+  for (int b = 0; b < p->nback[k]; ++b) {
+    const int x = p->back[k][b];
+    if (!p->has_elab) {
+      if (!has_edge(s->rp, s->col, w->f[x], v)) return 0;
+    } else {
+      const int64_t pos = edge_pos(s->rp, s->col, w->f[x], v);
+      if (pos < 0 || data_elab(s, pos) != p->elab[x][u]) return 0;
+    }
+  }
   if (s->induced)
     for (int b = 0; b < p->nnon[k]; ++b)
       if (has_edge(s->rp, s->col, w->f[p->non[k][b]], v)) return 0;
@@ -182,7 +218,7 @@ static void dfs(Worker *w, int k) {
   int32_t a = w->f[p->parent[k]];
   for (int64_t e = s->rp[a]; e < s->rp[a + 1]; ++e) {
     int32_t v = s->col[e];
-    if (!admissible(w, k, v)) continue;
+    if (!admissible(w, k, v, e)) continue;
     w->f[u] = v;
     w->used[v] = 1;
     dfs(w, k + 1);
@@ -203,7 +239,7 @@ static void *worker_main(void *arg) {
     if (b >= s->n) break;
     int64_t e = b + grain < s->n ? b + grain : s->n;
     for (int64_t v = b; v < e; ++v) {
-      if (!admissible(w, 0, (int32_t)v)) continue;
+      if (!admissible(w, 0, (int32_t)v, -1)) continue;
       w->f[p->order[0]] = (int32_t)v;
       w->used[v] = 1;
       dfs(w, 1);
@@ -219,17 +255,19 @@ static void *worker_main(void *arg) {
  * malloc'd array of count*q int32 (query-id columns, unsorted; release with
  * oracle_free).  nthreads <= 1 runs on the calling thread only.
  */
-int oracle_match_ex(int64_t n, const int64_t *rp, const int32_t *col, const int32_t *lab, int32_t q,
-                    int32_t ne, const int32_t *edges, const int32_t *qlab, int32_t root_q,
-                    uint32_t root_mod, uint32_t root_rem, int32_t want_rows, int32_t nthreads,
-                    int32_t induced, uint64_t *count, int32_t **rows_out) {
+int oracle_match_el(int64_t n, const int64_t *rp, const int32_t *col, const int32_t *lab,
+                    const int32_t *elab, int32_t q, int32_t ne, const int32_t *edges, const int32_t *qlab,
+                    const int32_t *qelab, int32_t root_q, uint32_t root_mod, uint32_t root_rem,
+                    int32_t want_rows, int32_t nthreads, int32_t induced, uint64_t *count,
+                    int32_t **rows_out) {
   OPlan p;
-  if (q < 1 || q > OQ_MAX || make_plan(q, ne, edges, qlab, &p) != 0) return -1;
+  if (q < 1 || q > OQ_MAX || make_plan(q, ne, edges, qlab, qelab, &p) != 0) return -1;
   Shared s;
   s.n = n;
   s.rp = rp;
   s.col = col;
   s.lab = lab;
+  s.elab = elab;
   s.p = &p;
   s.root_q = root_q;
   s.root_mod = root_mod;
@@ -285,6 +323,15 @@ int oracle_match_ex(int64_t n, const int64_t *rp, const int32_t *col, const int3
   pthread_mutex_destroy(&s.mu);
   if (rc == 0) *count = total;
   return rc;
+}
+
+/* oracle_match_el without edge labels. */
+int oracle_match_ex(int64_t n, const int64_t *rp, const int32_t *col, const int32_t *lab, int32_t q,
+                    int32_t ne, const int32_t *edges, const int32_t *qlab, int32_t root_q,
+                    uint32_t root_mod, uint32_t root_rem, int32_t want_rows, int32_t nthreads,
+                    int32_t induced, uint64_t *count, int32_t **rows_out) {
+  return oracle_match_el(n, rp, col, lab, NULL, q, ne, edges, qlab, NULL, root_q, root_mod, root_rem, want_rows,
+                         nthreads, induced, count, rows_out);
 }
 
 /* oracle_match_ex with non-induced semantics. */

@@ -96,6 +96,7 @@ class Graph:
     col: np.ndarray
     labels: Optional[np.ndarray] = None  # int32 per vertex, None = unlabelled
     name: str = ""
+    edge_labels: Optional[np.ndarray] = None  # int32 per CSR entry (both directions alike), None = none
 
     @property
     def n(self) -> int:
@@ -118,6 +119,7 @@ class Query:
     source: Optional[np.ndarray] = None  # data vertices the query was drawn from
     bound: float = -1.0                  # spanning-tree homomorphism bound
     name: str = ""
+    edge_labels: Optional[np.ndarray] = None  # int32 (ne,) per edge, None = unconstrained
 
     @property
     def ne(self) -> int:
@@ -331,6 +333,18 @@ def from_edges(n: int, edges, labels=None, name: str = "") -> Graph:
     rp = np.cumsum(rp)
     lab = None if labels is None else np.asarray(labels, dtype=np.int32)
     return Graph(rp, dst.astype(np.int32), lab, name)
+
+
+def with_edge_labels(g: Graph, L: int, seed: int) -> Graph:
+    """A copy of g whose undirected edges carry uniform labels in [0, L)
+    (numpy PCG64 seeded); both CSR entries of an edge get its label."""
+    n = g.n
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.row_ptr))
+    dst = g.col.astype(np.int64)
+    key = np.minimum(src, dst) * max(n, 1) + np.maximum(src, dst)
+    uniq, inv = np.unique(key, return_inverse=True)
+    lab = np.random.default_rng(seed).integers(0, max(L, 1), uniq.shape[0]).astype(np.int32)
+    return Graph(g.row_ptr, g.col, g.labels, g.name, lab[inv])
 
 
 def random_graph(n: int, p: float, L: int, seed: int) -> Graph:

@@ -25,4 +25,13 @@ def embeddings(g, qr, induced=False):
                 ok &= A[maps[:, a], maps[:, b]]
             elif induced:
                 ok &= ~A[maps[:, a], maps[:, b]]
+    qel = getattr(qr, "edge_labels", None)
+    if qel is not None:
+        # edge labels: the data edge's label (0 when the graph has none) must equal the query edge's
+        EL = np.zeros((n, n), dtype=np.int64)
+        gel = getattr(g, "edge_labels", None)
+        if gel is not None:
+            EL[src, g.col] = gel
+        for (a, b), lab in zip(np.asarray(qr.edges).reshape(-1, 2).tolist(), np.asarray(qel).tolist()):
+            ok &= EL[maps[:, a], maps[:, b]] == lab
     return maps[ok].astype(np.int32)  # permutations() is lexicographic: already sorted
