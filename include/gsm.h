@@ -90,6 +90,19 @@ typedef enum gsm_status {
  */
 gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col,
                             const int32_t *labels, uint32_t flags, gsm_graph_t *out);
+
+/*
+ * gsm_graph_create with edge labels (the labelled graphs of Sec. 3.1 carry
+ * node and edge labels).
+ *   edge_labels  row_ptr[n] labels >= 0, one per CSR entry, aligned with col;
+ *                both entries of an edge carry its label (checked under
+ *                GSM_GRAPH_VALIDATE); device memory with GSM_GRAPH_DEVICE_PTRS;
+ *                NULL = no edge labels (every edge then has label 0 for
+ *                edge-labelled queries)
+ * GSM_E_UNSUPPORTED with GSM_GRAPH_STRIP (cleaning reorders the entries).
+ */
+gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *labels,
+                               const int32_t *edge_labels, uint32_t flags, gsm_graph_t *out);
 void gsm_graph_destroy(gsm_graph_t g);
 
 /* n, CSR entries (2m), largest label, largest degree. Any out pointer may be NULL. */
@@ -120,6 +133,16 @@ void gsm_query_destroy(gsm_query_t qh);
  */
 gsm_status gsm_query_symmetry(gsm_query_t qh, uint64_t *aut, int32_t *pairs, int32_t pairs_cap,
                               int32_t *npairs);
+
+/*
+ * Gives every query edge a label >= 0 (edge_labels[e] for the e-th edge
+ * passed to gsm_query_create): an embedding must then map each query edge
+ * onto a data edge with the same label.  Recomputes the query's symmetry
+ * (automorphisms must keep edge labels).  Edge-labelled queries are matched
+ * by gsm_match only: gsm_match_batch and gsm_server_submit return
+ * GSM_E_UNSUPPORTED.
+ */
+gsm_status gsm_query_set_edge_labels(gsm_query_t qh, const int32_t *edge_labels);
 
 /*
  * The host pre-computation of Alg. 1 (PreCompute_on_CPUs, Sec. 3.2): query

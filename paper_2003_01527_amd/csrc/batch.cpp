@@ -52,7 +52,7 @@ struct BatchMatcher {
   BatchMatcher(gsm_graph &g_, const gsm_query *const *q_, int nq_, Workspace &ws_, hipStream_t s_)
       : g(g_), qs(q_, q_ + nq_), ws(ws_), s(s_), nq(nq_) {
     dg = DeviceGraph{g.rp,  g.col,  g.lab, g.deg, g.ne0, g.dne, g.col_lab ? g.col_lab : g.col,
-                     g.loff, g.loff_stride, g.n};
+                     g.loff, g.loff_stride, g.n, g.elab, g.elab_lab ? g.elab_lab : g.elab};
     dcnt = ws.counters.as<uint64_t>();
     for (auto *q : qs) {
       plans.push_back(make_plan(g, *q));
@@ -330,11 +330,16 @@ extern "C" gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query
       gsm::set_error("gsm_match_batch: at most 65535 queries per batch");
       return GSM_E_INVALID_ARG;
     }
-    for (int k = 0; k < nq; ++k)
+    for (int k = 0; k < nq; ++k) {
       if (!qs[k]) {
         gsm::set_error("gsm_match_batch: NULL query");
         return GSM_E_INVALID_ARG;
       }
+      if (qs[k]->has_elab) {
+        gsm::set_error("gsm_match_batch: edge-labelled queries are matched one at a time (gsm_match)");
+        return GSM_E_UNSUPPORTED;
+      }
+    }
     if (nq == 0) return GSM_OK;
     gsm_match_opts d;
     gsm_match_opts_init(&d);

@@ -59,6 +59,24 @@ void build_label_table(gsm_graph &g, const int64_t *rp, const int32_t *col, cons
   g.loff_stride = stride;
 }
 
+// Edge labels in col_lab order: the same stable per-row grouping by
+// neighbour label that build_label_table applies to col.
+void build_edge_label_table(gsm_graph &g, const int64_t *rp, const int32_t *col, const int32_t *lab,
+                            const int32_t *elab) {
+  if (!g.col_lab || !elab) return;
+  const int32_t L = g.max_label + 1;
+  std::vector<int32_t> el((size_t)std::max<int64_t>(g.nnz, 1));
+  std::vector<uint32_t> cnt(L + 1);
+  for (int64_t v = 0; v < g.n; ++v) {
+    std::fill(cnt.begin(), cnt.end(), 0u);
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k) cnt[lab[col[k]] + 1]++;
+    for (int32_t l = 0; l < L; ++l) cnt[l + 1] += cnt[l];
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k) el[rp[v] + cnt[lab[col[k]]]++] = elab[k];
+  }
+  GSM_HIP(hipMalloc((void **)&g.elab_lab, el.size() * sizeof(int32_t)));
+  GSM_HIP(hipMemcpy(g.elab_lab, el.data(), el.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+}
+
 Workspace::Workspace() {
   counters.reserve(64 * sizeof(uint64_t));
   scan_scratch.reserve(scan_scratch_elems() * sizeof(uint64_t));
@@ -198,6 +216,28 @@ static gsm_status strip_csr(int64_t n, const int64_t *rp, const int32_t *col, st
   return GSM_OK;
 }
 
+gsm_status gsm_query_set_edge_labels(gsm_query_t qh, const int32_t *edge_labels) {
+  GSM_API_BEGIN
+  if (!qh || (!edge_labels && !qh->edges.empty())) {
+    gsm::set_error("gsm_query_set_edge_labels: NULL argument");
+    return GSM_E_INVALID_ARG;
+  }
+  const size_t ne = qh->edges.size() / 2;
+  for (size_t e = 0; e < ne; ++e)
+    if (edge_labels[e] < 0) {
+      gsm::set_error("negative query edge label");
+      return GSM_E_BAD_QUERY;
+    }
+  for (size_t e = 0; e < ne; ++e) {
+    const int32_t a = qh->edges[2 * e], b = qh->edges[2 * e + 1];
+    qh->elab[a][b] = qh->elab[b][a] = edge_labels[e];
+  }
+  qh->has_elab = true;
+  gsm::compute_symmetry(*qh);  // automorphisms must keep edge labels too
+  return GSM_OK;
+  GSM_API_END
+}
+
 gsm_status gsm_query_symmetry(gsm_query_t qh, uint64_t *aut, int32_t *pairs, int32_t pairs_cap,
                               int32_t *npairs) {
   GSM_API_BEGIN
@@ -218,7 +258,16 @@ gsm_status gsm_query_symmetry(gsm_query_t qh, uint64_t *aut, int32_t *pairs, int
 
 gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col,
                             const int32_t *labels, uint32_t flags, gsm_graph_t *out) {
+  return gsm_graph_create_ex(n, row_ptr, col, labels, nullptr, flags, out);
+}
+
+gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *labels,
+                               const int32_t *edge_labels, uint32_t flags, gsm_graph_t *out) {
   GSM_API_BEGIN
+  if (edge_labels && (flags & GSM_GRAPH_STRIP)) {
+    gsm::set_error("gsm_graph_create_ex: edge labels cannot be combined with GSM_GRAPH_STRIP");
+    return GSM_E_UNSUPPORTED;
+  }
   if (!out || n < 0 || n >= (int64_t(1) << 31) || !row_ptr) {
     gsm::set_error("gsm_graph_create: invalid arguments");
     return GSM_E_INVALID_ARG;
@@ -239,7 +288,7 @@ gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *co
       gsm::set_error("row_ptr[n] < 0");
       return GSM_E_BAD_GRAPH;
     }
-    if ((flags & (GSM_GRAPH_VALIDATE | GSM_GRAPH_STRIP)) || labels) {
+    if ((flags & (GSM_GRAPH_VALIDATE | GSM_GRAPH_STRIP)) || labels || edge_labels) {
       h_col_store.resize(nnz);
       if (nnz)
         GSM_HIP(hipMemcpy(h_col_store.data(), col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -274,6 +323,32 @@ gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *co
   if (flags & GSM_GRAPH_VALIDATE) {
     gsm_status st = validate_csr(n, h_rp, h_col);
     if (st != GSM_OK) return st;
+  }
+  // edge labels: host view, non-negative, equal in both directions
+  std::vector<int32_t> h_el_store;
+  const int32_t *h_el = edge_labels;
+  if (edge_labels && dev) {
+    h_el_store.resize(nnz);
+    if (nnz) GSM_HIP(hipMemcpy(h_el_store.data(), edge_labels, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    h_el = h_el_store.data();
+  }
+  if (h_el) {
+    for (int64_t k = 0; k < nnz; ++k)
+      if (h_el[k] < 0) {
+        gsm::set_error("negative edge label at CSR entry " + std::to_string(k));
+        return GSM_E_BAD_GRAPH;
+      }
+    if (flags & GSM_GRAPH_VALIDATE)
+      for (int64_t v = 0; v < n; ++v)
+        for (int64_t k = h_rp[v]; k < h_rp[v + 1]; ++k) {
+          const int32_t w = h_col[k];
+          const int32_t *b = h_col + h_rp[w], *e = h_col + h_rp[w + 1];
+          const int32_t *it = std::lower_bound(b, e, (int32_t)v);
+          if (h_el[h_rp[w] + (it - b)] != h_el[k]) {
+            gsm::set_error("edge " + std::to_string(v) + "-" + std::to_string(w) + " has two labels");
+            return GSM_E_BAD_GRAPH;
+          }
+        }
   }
   int32_t max_label = 0;
   if (h_lab)
@@ -318,6 +393,11 @@ gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *co
     for (int64_t v = 0; v < n; ++v) g->deg_ge[h_rp[v + 1] - h_rp[v]]++;
     for (int64_t d = maxd; d >= 0; --d) g->deg_ge[d] += g->deg_ge[d + 1];
     gsm::build_label_table(*g, h_rp, h_col, h_lab);
+    if (h_el) {
+      GSM_HIP(hipMalloc((void **)&g->elab, std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+      if (nnz) GSM_HIP(hipMemcpy(g->elab, h_el, nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+      gsm::build_edge_label_table(*g, h_rp, h_col, h_lab, h_el);
+    }
     g->nheavy = (int64_t)heavy.size();
     if (!heavy.empty()) {
       GSM_HIP(hipMalloc((void **)&g->heavy, heavy.size() * sizeof(int32_t)));
@@ -346,6 +426,8 @@ void gsm_graph_destroy(gsm_graph_t g) {
   (void)hipFree(g->heavy);
   (void)hipFree(g->col_lab);
   (void)hipFree(g->loff);
+  (void)hipFree(g->elab);
+  (void)hipFree(g->elab_lab);
   delete g;
 }
 

@@ -73,6 +73,9 @@ struct gsm_graph {
   // loff[v * loff_stride + l] is where label l starts inside that row.
   int32_t *col_lab = nullptr;
   uint32_t *loff = nullptr;
+  // edge labels per CSR entry (aligned with col), and in col_lab order; null = none
+  int32_t *elab = nullptr;
+  int32_t *elab_lab = nullptr;
   int32_t loff_stride = 0;  // labels + 1, or 0 when there is no table
   // host statistics for the planner
   std::vector<int64_t> label_count;  // vertices per label
@@ -86,6 +89,9 @@ struct gsm_query {
   std::vector<int32_t> edges;  // 2*ne
   int32_t label[gsm::kMaxQ] = {0};
   uint32_t adj[gsm::kMaxQ] = {0};  // adjacency bitmask by query id
+  // edge labels (has_elab): elab[a][b] = label of query edge {a, b}
+  bool has_elab = false;
+  int32_t elab[gsm::kMaxQ][gsm::kMaxQ] = {{0}};
   // symmetry: |Aut(Q)| and constraints f(sym_pairs[2k]) < f(sym_pairs[2k+1])
   uint64_t aut = 1;
   std::vector<int32_t> sym_pairs;
@@ -147,6 +153,10 @@ struct LevelArgs {
   // induced mode: positions j < i not adjacent to position i, whose ids must
   // not be neighbours of the new vertex
   uint32_t non_mask;
+  // edge labels: when use_elab, the edge to earlier neighbour position j must
+  // carry label elab_req[j]
+  int32_t use_elab;
+  int32_t elab_req[kMaxQ];
   int32_t la_n;
   int32_t la_label[kMaxQ];
   uint32_t la_qbit[kMaxQ];
@@ -169,6 +179,8 @@ struct DeviceGraph {
   const uint32_t *loff;    // label offsets per row, or null
   int32_t loff_stride;
   int64_t n;
+  const int32_t *elab;         // edge label per col entry, or null (every edge has label 0)
+  const int32_t *elab_gather;  // edge label per gather entry, or null
 };
 
 // Each launcher enqueues on `s` and returns immediately.

@@ -81,6 +81,22 @@ __device__ __forceinline__ bool has_edge(const DeviceGraph &g, int32_t x, int32_
   return c[lo] == w;
 }
 
+// Position of w in the sorted neighbour list of x (an index into col), or -1.
+__device__ __forceinline__ int64_t edge_pos(const DeviceGraph &g, int32_t x, int32_t w, uint32_t &probes) {
+  const int64_t b = g.rp[x];
+  const int32_t *c = g.col + b;
+  uint32_t n = (uint32_t)(g.rp[x + 1] - b);
+  if (n == 0) return -1;
+  uint32_t lo = 0;
+  probes += n > 1 ? 33 - __builtin_clz(n - 1) : 1;
+  while (n > 1) {
+    const uint32_t half = n >> 1;
+    lo = (c[lo + half] <= w) ? lo + half : lo;
+    n -= half;
+  }
+  return c[lo] == w ? b + lo : -1;
+}
+
 // ------------------------------------------------------------ graph stats --
 
 // deg[v] and NE0[v] = sum over neighbours of (label+1); 16 lanes per vertex.
@@ -448,7 +464,9 @@ __global__ __launch_bounds__(kScanWG) void k_scan_down(const uint32_t *W, const 
 // prefix, one atomic per tile) so consecutive lanes write consecutive rows;
 // output rows are staged in LDS and copied out with contiguous stores when
 // they fit.
-template <int WG, int ITEMS, int MODE>
+// EXT: edge labels or induced semantics are in force (a separate
+// instantiation, so the common one carries none of their registers).
+template <int WG, int ITEMS, int MODE, bool EXT>
 __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
   constexpr bool BATCHED = (MODE == kModeBatch || MODE == kModeBatchLast);
   constexpr int TILE = WG * ITEMS;
@@ -633,15 +651,23 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
           const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
           keep = keep && (((a.L.sym_lt >> j) & 1) ? x < w : x > w);
         }
+        // edge labels: the anchor edge, then each back-edge below
+        if (EXT && a.L.use_elab && keep)
+          keep = (a.g.elab_gather ? a.g.elab_gather[ab[it] + off[it]] : 0) == a.L.elab_req[ap[it]];
         for (uint32_t m = p_nbr[it]; m; m &= m - 1) {
           const int j = __builtin_ctz(m);
           if (keep && j != ap[it]) {
             const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
-            keep = has_edge(a.g, x, w, probes);
+            if (EXT && a.L.use_elab) {
+              const int64_t pos = edge_pos(a.g, x, w, probes);
+              keep = pos >= 0 && (a.g.elab ? a.g.elab[pos] : 0) == a.L.elab_req[j];
+            } else {
+              keep = has_edge(a.g, x, w, probes);
+            }
           }
         }
         // induced mode: no edge to the earlier non-neighbours either
-        for (uint32_t m = a.L.non_mask; m; m &= m - 1) {
+        for (uint32_t m = EXT ? a.L.non_mask : 0u; m; m &= m - 1) {
           const int j = __builtin_ctz(m);
           if (keep) {
             const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
@@ -880,21 +906,32 @@ void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
                  ? 1
                  : 0;
   const size_t smem = (a.stage_in ? in_bytes : 0) + (a.staged ? out_bytes : 0);
+  const dim3 gd((uint32_t)grid), bd(WG);
+  const bool el = a.L.use_elab != 0 || a.L.non_mask != 0;
   switch (mode) {
     case kModeNext:
-      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeNext>), dim3((uint32_t)grid), dim3(WG), smem, s, a);
+      if (el)
+        hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeNext, true>), gd, bd, smem, s, a);
+      else
+        hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeNext, false>), gd, bd, smem, s, a);
       break;
     case kModeCount:
-      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeCount>), dim3((uint32_t)grid), dim3(WG), smem, s, a);
+      if (el)
+        hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeCount, true>), gd, bd, smem, s, a);
+      else
+        hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeCount, false>), gd, bd, smem, s, a);
       break;
     case kModeBatch:
-      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeBatch>), dim3((uint32_t)grid), dim3(WG), smem, s, a);
+      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeBatch, false>), gd, bd, smem, s, a);
       break;
     case kModeBatchLast:
-      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeBatchLast>), dim3((uint32_t)grid), dim3(WG), smem, s, a);
+      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeBatchLast, false>), gd, bd, smem, s, a);
       break;
     default:
-      hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeEmit>), dim3((uint32_t)grid), dim3(WG), smem, s, a);
+      if (el)
+        hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeEmit, true>), gd, bd, smem, s, a);
+      else
+        hipLaunchKernelGGL((k_expand<WG, ITEMS, kModeEmit, false>), gd, bd, smem, s, a);
       break;
   }
 }

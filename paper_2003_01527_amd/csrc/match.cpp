@@ -116,7 +116,7 @@ struct Matcher {
       : g(g_), qh(q_), o(o_), ws(ws_), s(o_.stream) {
     p = make_plan(g, qh);
     dg = DeviceGraph{g.rp,  g.col,  g.lab, g.deg, g.ne0, g.dne, g.col_lab ? g.col_lab : g.col,
-                     g.loff, g.loff_stride, g.n};
+                     g.loff, g.loff_stride, g.n, g.elab, g.elab_lab ? g.elab_lab : g.elab};
     dcnt = ws.counters.as<uint64_t>();
     std::memset(&st, 0, sizeof(st));
     st.struct_size = sizeof(st);
@@ -252,6 +252,11 @@ struct Matcher {
       L.in_pos[p.order[j]] = j;
     }
     if (o.induced) L.non_mask = ((1u << i) - 1u) & ~p.backmask[i];
+    if (qh.has_elab) {
+      L.use_elab = 1;
+      for (int j = 0; j < i; ++j)
+        if ((p.backmask[i] >> j) & 1) L.elab_req[j] = qh.elab[p.order[i]][p.order[j]];
+    }
     if (o.unique) {
       // symmetry-breaking constraints whose later vertex is placed at position i
       for (size_t k = 0; k + 1 < qh.sym_pairs.size(); k += 2) {

@@ -95,8 +95,11 @@ bool find_automorphism(const gsm_query &q, uint32_t fixed, int v, int w) {
   auto consistent = [&](int u, int x) {
     if (q.label[u] != q.label[x]) return false;
     if (__builtin_popcount(q.adj[u]) != __builtin_popcount(q.adj[x])) return false;
-    for (int t = 0; t < q.q; ++t)
-      if (img[t] >= 0 && t != u && (((q.adj[u] >> t) & 1) != ((q.adj[x] >> img[t]) & 1))) return false;
+    for (int t = 0; t < q.q; ++t) {
+      if (img[t] < 0 || t == u) continue;
+      if (((q.adj[u] >> t) & 1) != ((q.adj[x] >> img[t]) & 1)) return false;
+      if (q.has_elab && ((q.adj[u] >> t) & 1) && q.elab[u][t] != q.elab[x][img[t]]) return false;
+    }
     return true;
   };
   // the pre-placed vertices must agree with each other

@@ -203,6 +203,10 @@ gsm_status gsm_server_submit(gsm_server_t srv, gsm_query_t qh, uint64_t *ticket)
     gsm::set_error("gsm_server_submit: NULL argument");
     return GSM_E_INVALID_ARG;
   }
+  if (qh->has_elab) {
+    gsm::set_error("gsm_server_submit: edge-labelled queries are matched one at a time (gsm_match)");
+    return GSM_E_UNSUPPORTED;
+  }
   auto r = new Request();
   r->q = *qh;
   std::memset(&r->res, 0, sizeof(r->res));

@@ -100,6 +100,8 @@ def _load():
     lib.gsm_last_error.argtypes = []
     lib.gsm_graph_create.restype = ctypes.c_int
     lib.gsm_graph_create.argtypes = [i64, vp, vp, vp, u32, P(vp)]
+    lib.gsm_graph_create_ex.argtypes = [i64, vp, vp, vp, vp, u32, P(vp)]
+    lib.gsm_query_set_edge_labels.argtypes = [vp, vp]
     lib.gsm_graph_destroy.argtypes = [vp]
     lib.gsm_graph_info.restype = ctypes.c_int
     lib.gsm_graph_info.argtypes = [vp, P(i64), P(i64), P(i32), P(i64)]
@@ -146,28 +148,29 @@ def _p(a: Optional[np.ndarray]):
 class Graph:
     """A data graph uploaded to the device (simple, undirected, sorted CSR)."""
 
-    def __init__(self, row_ptr, col, labels=None, validate: bool = False, strip: bool = False):
+    def __init__(self, row_ptr, col, labels=None, validate: bool = False, strip: bool = False,
+                 edge_labels=None):
         lib = _load()
         flags = (GRAPH_VALIDATE if validate else 0) | (GRAPH_STRIP if strip else 0)
         self._h = ctypes.c_void_p()
         if hasattr(row_ptr, "data_ptr"):  # torch tensors on the device
             flags |= GRAPH_DEVICE_PTRS
             n = int(row_ptr.shape[0]) - 1
-            _check(lib.gsm_graph_create(n, ctypes.c_void_p(row_ptr.data_ptr()),
-                                        ctypes.c_void_p(col.data_ptr()),
-                                        None if labels is None else ctypes.c_void_p(labels.data_ptr()),
-                                        flags, ctypes.byref(self._h)))
+            dp = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+            _check(lib.gsm_graph_create_ex(n, dp(row_ptr), dp(col), dp(labels), dp(edge_labels), flags,
+                                           ctypes.byref(self._h)))
         else:
             rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
             cl = np.ascontiguousarray(col, dtype=np.int32)
             lb = None if labels is None else np.ascontiguousarray(labels, dtype=np.int32)
+            el = None if edge_labels is None else np.ascontiguousarray(edge_labels, dtype=np.int32)
             n = int(rp.shape[0]) - 1
-            _check(lib.gsm_graph_create(n, _p(rp), _p(cl), _p(lb), flags, ctypes.byref(self._h)))
+            _check(lib.gsm_graph_create_ex(n, _p(rp), _p(cl), _p(lb), _p(el), flags, ctypes.byref(self._h)))
         self.n = n
 
     @classmethod
     def from_workload(cls, g, validate: bool = False):
-        return cls(g.row_ptr, g.col, g.labels, validate)
+        return cls(g.row_ptr, g.col, g.labels, validate, edge_labels=getattr(g, "edge_labels", None))
 
     def info(self):
         n, nnz, ml, md = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
@@ -190,17 +193,20 @@ class Graph:
 class Query:
     """A connected query graph (1..16 vertices)."""
 
-    def __init__(self, q: int, edges, labels=None):
+    def __init__(self, q: int, edges, labels=None, edge_labels=None):
         lib = _load()
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
         lb = None if labels is None else np.ascontiguousarray(labels, dtype=np.int32)
         self._h = ctypes.c_void_p()
         _check(lib.gsm_query_create(int(q), int(e.shape[0]), _p(e), _p(lb), ctypes.byref(self._h)))
         self.q = int(q)
+        if edge_labels is not None:
+            el = np.ascontiguousarray(edge_labels, dtype=np.int32)
+            _check(lib.gsm_query_set_edge_labels(self._h, _p(el)))
 
     @classmethod
     def from_workload(cls, qr):
-        return cls(qr.q, qr.edges, qr.labels)
+        return cls(qr.q, qr.edges, qr.labels, getattr(qr, "edge_labels", None))
 
     def close(self):
         if self._h:

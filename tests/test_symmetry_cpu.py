@@ -100,3 +100,29 @@ def test_shapes_in_complete_graph():
     aut, pairs = gsm.symmetry(gsm.Query.from_workload(qr))
     c, rows = oracle.match(g, qr)
     assert satisfies(rows, pairs).sum() == comb(7, 4) == c // aut
+
+
+def brute_aut_edge_labels(qr):
+    q = qr.q
+    lab = np.zeros(q, np.int64) if qr.labels is None else np.asarray(qr.labels)
+    E = {frozenset(e): int(l) for e, l in zip(np.asarray(qr.edges).reshape(-1, 2).tolist(), qr.edge_labels)}
+    n = 0
+    for p in itertools.permutations(range(q)):
+        if all(lab[p[u]] == lab[u] for u in range(q)) and \
+                {frozenset((p[a], p[b])): l for (a, b), l in ((tuple(e), l) for e, l in E.items())} == E:
+            n += 1
+    return n
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_aut_with_edge_labels(seed):
+    rng = np.random.default_rng(7_000 + seed)
+    qr = W.random_query(int(rng.integers(2, 7)), float(rng.uniform(0.2, 0.9)), int(rng.integers(0, 2)), seed)
+    qr.edge_labels = rng.integers(0, int(rng.integers(1, 3)), qr.ne).astype(np.int32)
+    got, pairs = gsm.symmetry(gsm.Query.from_workload(qr))
+    assert got == brute_aut_edge_labels(qr)
+    g = W.with_edge_labels(W.random_graph(int(rng.integers(5, 16)), 0.5, 0 if qr.labels is None else 2, seed),
+                           2, seed + 1)
+    c, rows = oracle.match(g, qr)
+    kept = rows[satisfies(rows, pairs)]
+    assert kept.shape[0] * got == c
