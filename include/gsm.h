@@ -140,7 +140,8 @@ gsm_status gsm_query_symmetry(gsm_query_t qh, uint64_t *aut, int32_t *pairs, int
  * onto a data edge with the same label.  Recomputes the query's symmetry
  * (automorphisms must keep edge labels).  Edge-labelled queries are matched
  * by gsm_match only: gsm_match_batch and gsm_server_submit return
- * GSM_E_UNSUPPORTED.
+ * GSM_E_UNSUPPORTED.  Call it before the query is first used: a query that
+ * another thread is matching must not change.
  */
 gsm_status gsm_query_set_edge_labels(gsm_query_t qh, const int32_t *edge_labels);
 
