@@ -219,3 +219,39 @@ def test_graph_validation_on_device_errors():
     col = np.array([2, 1, 0, 0], np.int32)
     with pytest.raises(gsm.GsmError):
         gsm.Graph(rp, col, validate=True)
+
+
+@pytest.mark.parametrize("extra", [1 << 12, 1 << 16, 1 << 22])
+def test_device_sink_chunks(powerlaw, extra):
+    """Rows handed to a device sink chunk by chunk are exactly the oracle's,
+    for several chunk sizes; a sink that stops early cancels the match."""
+    import ctypes
+    import torch
+    w, G = powerlaw
+    qr = w.queries[9]
+    root = (0, 32, 1)
+    c, r = oracle.match(w.graph, qr, threads=NCPU, root=root)
+    Q = gsm.Query.from_workload(qr)
+    lib = ctypes.CDLL("libamdhip64.so.7")
+    seen = []
+
+    def sink(ptr, nrows, q):
+        buf = torch.empty((nrows, q), dtype=torch.int32)
+        assert lib.hipMemcpy(ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(ptr),
+                             ctypes.c_size_t(nrows * q * 4), 2) == 0
+        seen.append(buf.numpy().copy())
+        return False
+    budget = gsm.min_budget(G, Q, host_rows=True) + extra
+    cg, _, st = gsm.match(G, Q, emit_device=sink, root=root, budget=budget)
+    assert cg == c
+    np.testing.assert_array_equal(oracle.sort_rows(np.concatenate(seen)), r)
+    calls = []
+
+    def stop(ptr, nrows, q):
+        calls.append(nrows)
+        return len(calls) >= 2
+    try:
+        gsm.match(G, Q, emit_device=stop, root=root, budget=budget)
+        assert len(calls) < 2  # finished before a second chunk
+    except gsm.GsmError as e:
+        assert e.status == 8 and len(calls) == 2
