@@ -280,7 +280,9 @@ void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_
     const uint64_t heavy_pairs = o.batch_heavy_pairs ? o.batch_heavy_pairs : (uint64_t(1) << 18);
     std::vector<int> light;
     std::vector<int> heavy;
-    {
+    if (heavy_pairs == UINT64_MAX) {  // every query shares launches: nothing to estimate
+      for (int k = 0; k < nq; ++k) light.push_back(k);
+    } else {
       BatchMatcher est(g, qs, nq, ws, stream);
       configure(est);
       const std::vector<uint64_t> p1 = est.first_level_pairs();
