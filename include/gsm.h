@@ -122,7 +122,8 @@ gsm_status gsm_query_create(int32_t q, int32_t ne, const int32_t *edges, const i
 void gsm_query_destroy(gsm_query_t qh);
 
 /*
- * Symmetry of a query (host only, computed at gsm_query_create): aut gets
+ * Symmetry of a query for the unique-subgraph mode (producing each node
+ * combination once, Sec. 3.3; host only, computed at gsm_query_create): aut gets
  * |Aut(Q)|, the number of automorphisms (label- and edge-preserving
  * permutations of the query vertices); pairs gets up to pairs_cap constraints
  * as (a, b) query-id pairs meaning f(a) < f(b), npairs their number (at most
@@ -136,8 +137,9 @@ gsm_status gsm_query_symmetry(gsm_query_t qh, uint64_t *aut, int32_t *pairs, int
 
 /*
  * Gives every query edge a label >= 0 (edge_labels[e] for the e-th edge
- * passed to gsm_query_create): an embedding must then map each query edge
- * onto a data edge with the same label.  Recomputes the query's symmetry
+ * passed to gsm_query_create; the node- and edge-labelled graphs of Sec. 3.1):
+ * an embedding must then map each query edge onto a data edge with the same
+ * label.  The labels are copied; GSM_E_BAD_QUERY for a negative label.  Recomputes the query's symmetry
  * (automorphisms must keep edge labels).  Edge-labelled queries are matched
  * by gsm_match only: gsm_match_batch and gsm_server_submit return
  * GSM_E_UNSUPPORTED.  Call it before the query is first used: a query that
