@@ -150,6 +150,9 @@ struct LevelArgs {
   // unique-subgraph mode: positions j < i whose id must be below (sym_lt)
   // or above (sym_gt) the new vertex's id
   uint32_t sym_lt, sym_gt;
+  // and the same for position i+1 against positions j <= i (j = i: the new
+  // vertex): the next range is cut to the ids they allow (kModeNext)
+  uint32_t next_sym_lt, next_sym_gt;
   // induced mode: positions j < i not adjacent to position i, whose ids must
   // not be neighbours of the new vertex
   uint32_t non_mask;

@@ -693,6 +693,43 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
               bb = base;
             }
           }
+          if (EXT && MODE == kModeNext && best > 0 && (a.L.next_sym_lt | a.L.next_sym_gt)) {
+            // unique mode: keep only the ids the next position's order
+            // constraints allow; the range is sorted by id, so it narrows to
+            // the ids in (lo, hi) by two halving searches
+            int64_t lo = -1, hi = (int64_t)1 << 31;
+            for (uint32_t mm = a.L.next_sym_lt | a.L.next_sym_gt; mm; mm &= mm - 1) {
+              const int j = __builtin_ctz(mm);
+              const int32_t x = (j == i) ? w : (stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j]);
+              if ((a.L.next_sym_lt >> j) & 1)
+                lo = max(lo, (int64_t)x);
+              else
+                hi = min(hi, (int64_t)x);
+            }
+            const int32_t *r = a.g.gather + bb;
+            uint32_t f = 0, n = best;  // first entry > lo
+            while (n > 0) {
+              const uint32_t h = n >> 1;
+              if ((int64_t)r[f + h] <= lo) {
+                f += h + 1;
+                n -= h + 1;
+              } else {
+                n = h;
+              }
+            }
+            uint32_t e = f, m = best - f;  // first entry >= hi
+            while (m > 0) {
+              const uint32_t h = m >> 1;
+              if ((int64_t)r[e + h] < hi) {
+                e += h + 1;
+                m -= h + 1;
+              } else {
+                m = h;
+              }
+            }
+            bb += f;
+            best = e - f;
+          }
           keep = best > 0;
           nW[it] = best;
           nbase[it] = bb;
@@ -907,7 +944,7 @@ void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
                  : 0;
   const size_t smem = (a.stage_in ? in_bytes : 0) + (a.staged ? out_bytes : 0);
   const dim3 gd((uint32_t)grid), bd(WG);
-  const bool el = a.L.use_elab != 0 || a.L.non_mask != 0;
+  const bool el = a.L.use_elab != 0 || a.L.non_mask != 0 || (a.L.next_sym_lt | a.L.next_sym_gt) != 0;
   switch (mode) {
     case kModeNext:
       if (el)

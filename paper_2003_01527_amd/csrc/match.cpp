@@ -263,6 +263,8 @@ struct Matcher {
         const int pa = p.pos[qh.sym_pairs[k]], pb = p.pos[qh.sym_pairs[k + 1]];
         if (pb == i && pa < i) L.sym_lt |= 1u << pa;  // f(a) < f(b) = w
         if (pa == i && pb < i) L.sym_gt |= 1u << pb;  // w = f(a) < f(b)
+        if (pb == i + 1 && pa <= i) L.next_sym_lt |= 1u << pa;
+        if (pa == i + 1 && pb <= i) L.next_sym_gt |= 1u << pb;
       }
     }
     if (o.lookahead) {
