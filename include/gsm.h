@@ -351,6 +351,13 @@ uint64_t gsm_now_ns(void);
 /* ----------------------------------------------------------------- errors -- */
 
 const char *gsm_status_str(gsm_status s);
+
+/* ---------------------------------------------------------------- testing -- */
+
+/* Failure injection for tests of the error paths: after `after` more device
+ * allocations by the library, every further one fails (the call then returns
+ * GSM_E_OOM) until this is called again with after < 0.  Process-wide. */
+void gsm_testing_fail_allocations(int64_t after);
 const char *gsm_last_error(void); /* thread-local; "" when none */
 
 #ifdef __cplusplus

@@ -9,6 +9,7 @@
 // a pruning choice that never changes a count.
 #include <algorithm>
 #include <chrono>
+#include <exception>
 #include <cstring>
 
 #include <cstddef>
@@ -61,6 +62,11 @@ struct BatchMatcher {
   }
 
   void sync() { GSM_HIP(hipStreamSynchronize(s)); }
+
+  // launches of a call that fails part-way finish before the workspace is reused
+  ~BatchMatcher() {
+    if (std::uncaught_exceptions() > 0) (void)hipStreamSynchronize(s);
+  }
 
   void fetch_counters() {
     GSM_HIP(hipMemcpyAsync(ws.h_counters, dcnt, 64 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));

@@ -1,5 +1,6 @@
 // C ABI: errors, graph and query handles, the visiting-order query.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <new>
 
@@ -13,18 +14,35 @@ thread_local std::string g_last_error;
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 
+namespace {
+// failure injection for tests: number of device allocations still allowed,
+// or -1 for no limit
+std::atomic<int64_t> g_allocs_left{-1};
+}  // namespace
+
+void device_alloc(void **p, size_t bytes) {
+  int64_t left = g_allocs_left.load();
+  while (left >= 0) {
+    if (left == 0) {
+      *p = nullptr;
+      throw Error{GSM_E_OOM, "device allocation refused (failure injection)"};
+    }
+    if (g_allocs_left.compare_exchange_weak(left, left - 1)) break;
+  }
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    throw Error{GSM_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
+}
+
 void DevBuf::reserve(size_t want) {
   if (want <= bytes && ptr) return;
   if (ptr) (void)hipDeviceSynchronize();  // no pending kernel may still use the old buffer
   release();
   if (want == 0) return;
-  size_t b = (want + 255) & ~size_t(255);
-  hipError_t e = hipMalloc(&ptr, b);
-  if (e != hipSuccess) {
-    ptr = nullptr;
-    (void)hipGetLastError();
-    throw Error{GSM_E_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed"};
-  }
+  const size_t b = (want + 255) & ~size_t(255);
+  device_alloc(&ptr, b);
   bytes = b;
 }
 
@@ -52,9 +70,9 @@ void build_label_table(gsm_graph &g, const int64_t *rp, const int32_t *col, cons
     for (int32_t l = 0; l <= L; ++l) o[l] = cnt[l];
     for (int64_t k = rp[v]; k < rp[v + 1]; ++k) cl[rp[v] + cnt[lab[col[k]]]++] = col[k];
   }
-  GSM_HIP(hipMalloc((void **)&g.col_lab, cl.size() * sizeof(int32_t)));
+  device_alloc((void **)&g.col_lab, cl.size() * sizeof(int32_t));
   GSM_HIP(hipMemcpy(g.col_lab, cl.data(), cl.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  GSM_HIP(hipMalloc((void **)&g.loff, off.size() * sizeof(uint32_t)));
+  device_alloc((void **)&g.loff, off.size() * sizeof(uint32_t));
   GSM_HIP(hipMemcpy(g.loff, off.data(), off.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
   g.loff_stride = stride;
 }
@@ -73,7 +91,7 @@ void build_edge_label_table(gsm_graph &g, const int64_t *rp, const int32_t *col,
     for (int32_t l = 0; l < L; ++l) cnt[l + 1] += cnt[l];
     for (int64_t k = rp[v]; k < rp[v + 1]; ++k) el[rp[v] + cnt[lab[col[k]]]++] = elab[k];
   }
-  GSM_HIP(hipMalloc((void **)&g.elab_lab, el.size() * sizeof(int32_t)));
+  device_alloc((void **)&g.elab_lab, el.size() * sizeof(int32_t));
   GSM_HIP(hipMemcpy(g.elab_lab, el.data(), el.size() * sizeof(int32_t), hipMemcpyHostToDevice));
 }
 
@@ -215,6 +233,8 @@ static gsm_status strip_csr(int64_t n, const int64_t *rp, const int32_t *col, st
   }
   return GSM_OK;
 }
+
+void gsm_testing_fail_allocations(int64_t after) { gsm::g_allocs_left.store(after < 0 ? -1 : after); }
 
 gsm_status gsm_query_set_edge_labels(gsm_query_t qh, const int32_t *edge_labels) {
   GSM_API_BEGIN
@@ -366,16 +386,16 @@ gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t 
     g->labelled = labels != nullptr;
     g->max_label = max_label;
     const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    GSM_HIP(hipMalloc((void **)&g->rp, (n + 1) * sizeof(int64_t)));
+    gsm::device_alloc((void **)&g->rp, (n + 1) * sizeof(int64_t));
     GSM_HIP(hipMemcpy(g->rp, src_rp, (n + 1) * sizeof(int64_t), csr_kind));
-    GSM_HIP(hipMalloc((void **)&g->col, std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+    gsm::device_alloc((void **)&g->col, std::max<int64_t>(nnz, 1) * sizeof(int32_t));
     if (nnz) GSM_HIP(hipMemcpy(g->col, src_col, nnz * sizeof(int32_t), csr_kind));
-    GSM_HIP(hipMalloc((void **)&g->deg, std::max<int64_t>(n, 1) * sizeof(uint32_t)));
-    GSM_HIP(hipMalloc((void **)&g->dne, std::max<int64_t>(n, 1) * sizeof(uint2)));
+    gsm::device_alloc((void **)&g->deg, std::max<int64_t>(n, 1) * sizeof(uint32_t));
+    gsm::device_alloc((void **)&g->dne, std::max<int64_t>(n, 1) * sizeof(uint2));
     if (labels) {
-      GSM_HIP(hipMalloc((void **)&g->lab, std::max<int64_t>(n, 1) * sizeof(int32_t)));
+      gsm::device_alloc((void **)&g->lab, std::max<int64_t>(n, 1) * sizeof(int32_t));
       if (n) GSM_HIP(hipMemcpy(g->lab, labels, n * sizeof(int32_t), kind));
-      GSM_HIP(hipMalloc((void **)&g->ne0, std::max<int64_t>(n, 1) * sizeof(uint64_t)));
+      gsm::device_alloc((void **)&g->ne0, std::max<int64_t>(n, 1) * sizeof(uint64_t));
     }
     gsm::launch_graph_stats(*g, nullptr);
     // planner statistics and the high-degree vertex list
@@ -394,13 +414,13 @@ gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t 
     for (int64_t d = maxd; d >= 0; --d) g->deg_ge[d] += g->deg_ge[d + 1];
     gsm::build_label_table(*g, h_rp, h_col, h_lab);
     if (h_el) {
-      GSM_HIP(hipMalloc((void **)&g->elab, std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+      gsm::device_alloc((void **)&g->elab, std::max<int64_t>(nnz, 1) * sizeof(int32_t));
       if (nnz) GSM_HIP(hipMemcpy(g->elab, h_el, nnz * sizeof(int32_t), hipMemcpyHostToDevice));
       gsm::build_edge_label_table(*g, h_rp, h_col, h_lab, h_el);
     }
     g->nheavy = (int64_t)heavy.size();
     if (!heavy.empty()) {
-      GSM_HIP(hipMalloc((void **)&g->heavy, heavy.size() * sizeof(int32_t)));
+      gsm::device_alloc((void **)&g->heavy, heavy.size() * sizeof(int32_t));
       GSM_HIP(hipMemcpy(g->heavy, heavy.data(), heavy.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
     GSM_HIP(hipDeviceSynchronize());

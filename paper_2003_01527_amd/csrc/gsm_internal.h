@@ -34,6 +34,10 @@ struct Error {
 // ------------------------------------------------------------ device buffer --
 
 // Device allocation that grows on demand and is reused across calls.
+// hipMalloc that throws Error{GSM_E_OOM} on failure (and when the test hook
+// gsm_testing_fail_allocations has used up its allowance).
+void device_alloc(void **p, size_t bytes);
+
 struct DevBuf {
   void *ptr = nullptr;
   size_t bytes = 0;

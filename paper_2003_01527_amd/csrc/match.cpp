@@ -3,6 +3,7 @@
 // inside a chunk), as in the verification loop of the paper's Alg. 1.
 #include <algorithm>
 #include <chrono>
+#include <exception>
 #include <cstddef>
 #include <cstring>
 
@@ -121,6 +122,12 @@ struct Matcher {
     std::memset(&st, 0, sizeof(st));
     st.struct_size = sizeof(st);
     st.q = p.q;
+  }
+
+  // A call that fails part-way may have launches in flight on the stream;
+  // they must finish before the next call reuses the workspace buffers.
+  ~Matcher() {
+    if (std::uncaught_exceptions() > 0) (void)hipStreamSynchronize(s);
   }
 
   QueryArgs query_args() const {

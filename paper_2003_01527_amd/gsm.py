@@ -102,6 +102,8 @@ def _load():
     lib.gsm_graph_create.argtypes = [i64, vp, vp, vp, u32, P(vp)]
     lib.gsm_graph_create_ex.argtypes = [i64, vp, vp, vp, vp, u32, P(vp)]
     lib.gsm_query_set_edge_labels.argtypes = [vp, vp]
+    lib.gsm_testing_fail_allocations.argtypes = [i64]
+    lib.gsm_testing_fail_allocations.restype = None
     lib.gsm_graph_destroy.argtypes = [vp]
     lib.gsm_graph_info.restype = ctypes.c_int
     lib.gsm_graph_info.argtypes = [vp, P(i64), P(i64), P(i32), P(i64)]
@@ -374,6 +376,12 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def testing_fail_allocations(after: int) -> None:
+    """Test hook: after `after` more device allocations the library's
+    allocations fail with GSM_E_OOM; after < 0 lifts the limit."""
+    _load().gsm_testing_fail_allocations(int(after))
 
 
 def now_ns() -> int:
