@@ -71,3 +71,24 @@ def test_triangles_by_colour():
     assert counts == b
     assert sum(counts.values()) == 24
     assert counts[(0, 0, 0)] == 0  # no three vertices of one parity
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_generated_edge_labels_are_symmetric(seed):
+    g = W.with_edge_labels(W.random_graph(40, 0.2, 2, seed), 5, seed)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    lab = {(int(a), int(b)): int(l) for a, b, l in zip(src, g.col, g.edge_labels)}
+    assert all(lab[(b, a)] == l for (a, b), l in lab.items())
+    assert g.edge_labels.min() >= 0 and g.edge_labels.max() < 5
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_query_without_edge_labels_is_unconstrained(seed):
+    rng = np.random.default_rng(43_000 + seed)
+    g0 = W.random_graph(int(rng.integers(5, 25)), 0.4, 2, seed)
+    g = W.with_edge_labels(g0, 3, seed + 1)
+    qr = W.random_query(int(rng.integers(2, 5)), 0.4, 2, seed + 2)
+    c0, r0 = oracle.match(g0, qr)
+    c, r = oracle.match(g, qr)
+    assert c == c0
+    np.testing.assert_array_equal(r, r0)
