@@ -87,3 +87,20 @@ def test_match_rejects_null_handles():
     cnt = ctypes.c_uint64()
     assert lib.gsm_match(None, None, None, ctypes.byref(cnt), None, 0, None) == 1
     assert lib.gsm_match_batch(None, 0, None, None, None) == 1
+
+
+def test_binding_flags_match_header():
+    text = open(os.path.join(ROOT, "include", "gsm.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(GSM_\w+)\s+(\d+)u?", text)}
+    assert defs["GSM_GRAPH_VALIDATE"] == gsm.GRAPH_VALIDATE
+    assert defs["GSM_GRAPH_DEVICE_PTRS"] == gsm.GRAPH_DEVICE_PTRS
+    assert defs["GSM_GRAPH_STRIP"] == gsm.GRAPH_STRIP
+    assert defs["GSM_MATCH_NO_OUTPUT_STAGING"] == gsm.FLAG_NO_OUTPUT_STAGING
+    assert defs["GSM_MATCH_SORT_ROWS"] == gsm.FLAG_SORT_ROWS
+    assert defs["GSM_MATCH_LOOKAHEAD"] == gsm.FLAG_LOOKAHEAD
+    assert defs["GSM_MATCH_UNIQUE"] == gsm.FLAG_UNIQUE
+    assert defs["GSM_MATCH_INDUCED"] == gsm.FLAG_INDUCED
+    assert defs["GSM_MAX_QUERY_VERTICES"] == 16
+    flags = gsm.make_opts(sort_rows=True, lookahead=True, unique=True, induced=True, stage_output=False).flags
+    assert flags == (gsm.FLAG_SORT_ROWS | gsm.FLAG_LOOKAHEAD | gsm.FLAG_UNIQUE | gsm.FLAG_INDUCED
+                     | gsm.FLAG_NO_OUTPUT_STAGING)
