@@ -97,6 +97,16 @@ def test_filter_ne_worked_example():
     assert oracle.match(g, qr, rows=False)[0] == int(rec["count"][0])
 
 
+def test_filter_refinement_worked_example():
+    rec = records("filter_refine_example.txt")[0]
+    g = W.from_edges(int(rec["n"][0]), parse_edges(rec["edges"]))
+    qr = query_of(parse_edges(rec["query_edges"]))
+    for r in (0, 1, 2):
+        got = oracle.filter(g, qr, rounds=r)
+        assert got.tolist() == ints(rec["mask_r%d" % r]), r
+    assert oracle.match(g, qr, rows=False)[0] == int(rec["count"][0])
+
+
 @pytest.mark.parametrize("rec", records("plan_examples.txt"), ids=["A", "B"])
 def test_plan_worked_examples(rec):
     ge = parse_edges(rec["graph_edges"])
