@@ -300,7 +300,9 @@ gsm_status gsm_match_min_budget(gsm_graph_t g, gsm_query_t qh, int32_t host_rows
  * like one query).
  * Queries above opts->batch_heavy_pairs first-level pairs run on launches of
  * their own, where a query-uniform kernel is faster.  counts[k] equals
- * gsm_match's count for qs[k].  No root slice, rows or emit callback.
+ * gsm_match's count for qs[k].  A root slice in opts (root_qvertex,
+ * root_mod, root_rem) applies to every query (root_qvertex must be below
+ * every query's size).  No rows or emit callback.
  */
 gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query_t *qs,
                            const gsm_match_opts *opts, uint64_t *counts);
@@ -341,6 +343,14 @@ void gsm_server_opts_init(gsm_server_opts *o);
 gsm_status gsm_server_create(gsm_graph_t g, const gsm_server_opts *opts, gsm_server_t *out);
 /* Copies the query (the caller may destroy it on return); *ticket identifies the request. */
 gsm_status gsm_server_submit(gsm_server_t srv, gsm_query_t qh, uint64_t *ticket);
+/* gsm_server_submit restricted to a root slice (the gsm_match_opts
+ * convention): only embeddings with splitmix64(f(root_qvertex)) % root_mod ==
+ * root_rem are counted; root_qvertex < 0 = no slice.  Slices of one query
+ * over all residues partition its embeddings, so a large query can be served
+ * as root_mod independent requests.  GSM_E_INVALID_ARG unless
+ * root_qvertex < q and root_rem < root_mod. */
+gsm_status gsm_server_submit_slice(gsm_server_t srv, gsm_query_t qh, int32_t root_qvertex, uint32_t root_mod,
+                                   uint32_t root_rem, uint64_t *ticket);
 /* Waits for a ticket (timeout_ms < 0: forever) and releases it.  GSM_E_TIMEOUT if not done. */
 gsm_status gsm_server_wait(gsm_server_t srv, uint64_t ticket, int32_t timeout_ms, gsm_result *out);
 /* Finishes the admitted work, stops the workers, frees everything. */

@@ -49,9 +49,13 @@ struct BatchMatcher {
   std::vector<uint8_t> evicted;
   std::vector<uint64_t> h_qpairs;
   bool any_evicted = false;
+  std::vector<RootSlice> slices;  // per query
 
-  BatchMatcher(gsm_graph &g_, const gsm_query *const *q_, int nq_, Workspace &ws_, hipStream_t s_)
+  BatchMatcher(gsm_graph &g_, const gsm_query *const *q_, int nq_, Workspace &ws_, hipStream_t s_,
+               const RootSlice *sl)
       : g(g_), qs(q_, q_ + nq_), ws(ws_), s(s_), nq(nq_) {
+    slices.assign(nq, RootSlice{});
+    if (sl) slices.assign(sl, sl + nq);
     dg = DeviceGraph{g.rp,  g.col,  g.lab, g.deg, g.ne0, g.dne, g.col_lab ? g.col_lab : g.col,
                      g.loff, g.loff_stride, g.n, g.elab, g.elab_lab ? g.elab_lab : g.elab};
     dcnt = ws.counters.as<uint64_t>();
@@ -85,10 +89,12 @@ struct BatchMatcher {
       e.qlab = -1;
     }
     std::vector<FirstBatch> fb(nq);
+    std::memset(fb.data(), 0, fb.size() * sizeof(FirstBatch));
     for (int k = 0; k < nq; ++k) {
       const Plan &p = plans[k];
       for (int i = 0; i < p.q; ++i) {
         BatchLevel &e = bl[(size_t)k * kMaxQ + i];
+        std::memset(&e, 0, sizeof(e));
         e.nbr_mask = p.backmask[i];
         e.next_nbr_mask = (i + 1 < p.q) ? p.backmask[i + 1] : 0;
         e.next_label = (i + 1 < p.q) ? p.qlab[p.order[i + 1]] : 0;
@@ -99,6 +105,17 @@ struct BatchMatcher {
         e.qdeg = use_deg ? (uint32_t)p.qdeg[u] : 0;
         e.qne = use_ne ? std::min<uint64_t>(p.qne[u], 0xffffffffull) : 0;
       }
+      const RootSlice &rs = slices[k];
+      if (rs.qvertex >= 0) {  // the slice tests the position of the sliced query vertex
+        const int ps = p.pos[rs.qvertex];
+        if (ps == 0) {
+          fb[k].slice_mod = rs.mod;
+          fb[k].slice_rem = rs.rem;
+        } else {
+          bl[(size_t)k * kMaxQ + ps].slice_mod = rs.mod;
+          bl[(size_t)k * kMaxQ + ps].slice_rem = rs.rem;
+        }
+      }
       const int u0 = p.order[0];
       fb[k].qlab0 = p.qlab[u0];
       fb[k].qdeg0 = use_deg ? (uint32_t)p.qdeg[u0] : 0;
@@ -108,13 +125,13 @@ struct BatchMatcher {
     }
     const size_t b_bl = bl.size() * sizeof(BatchLevel), b_fb = nq * sizeof(FirstBatch);
     const size_t o_fb = (b_bl + 255) & ~size_t(255);
-    ws.tables.reserve(o_fb + b_fb);
+    ws.tables.reserve(o_fb + b_fb, s);
     char *base = ws.tables.as<char>();
     GSM_HIP(hipMemcpyAsync(base, bl.data(), b_bl, hipMemcpyHostToDevice, s));
     GSM_HIP(hipMemcpyAsync(base + o_fb, fb.data(), b_fb, hipMemcpyHostToDevice, s));
     d_bl = reinterpret_cast<BatchLevel *>(base);
     d_fb = reinterpret_cast<FirstBatch *>(base + o_fb);
-    ws.counts.reserve((nq + 1) * sizeof(uint64_t));
+    ws.counts.reserve((nq + 1) * sizeof(uint64_t), s);
     d_counts = ws.counts.as<uint64_t>();
     GSM_HIP(hipMemsetAsync(d_counts, 0, (nq + 1) * sizeof(uint64_t), s));
   }
@@ -133,20 +150,23 @@ struct BatchMatcher {
     const uint64_t rest = budget - fixed;
     const int shares = std::max(1, maxq - 2);
     // buffers kept from earlier calls count against this budget
-    uint64_t held = ws.emit.bytes + ws.tables.bytes + ws.counts.bytes;
+    uint64_t held = ws.emit.bytes + ws.tables.bytes + ws.counts.bytes + ws.qpairs.bytes + ws.evicted.bytes +
+                    ws.cmask.bytes + ws.cmask2.bytes;
     for (int i = 0; i < kMaxQ; ++i)
       held += ws.rows[i].bytes + ws.S[i].bytes + ws.W[i].bytes + ws.apos[i].bytes + ws.abase[i].bytes +
               ws.qid[i].bytes;
     if (held > budget) {
       for (int i = 0; i < kMaxQ; ++i) {
-        ws.rows[i].release();
-        ws.S[i].release();
-        ws.W[i].release();
-        ws.apos[i].release();
-        ws.abase[i].release();
-        ws.qid[i].release();
+        ws.rows[i].release(s);
+        ws.S[i].release(s);
+        ws.W[i].release(s);
+        ws.apos[i].release(s);
+        ws.abase[i].release(s);
+        ws.qid[i].release(s);
       }
-      ws.emit.release();
+      ws.emit.release(s);
+      ws.cmask.release(s);
+      ws.cmask2.release(s);
     }
     for (int i = 0; i < kMaxQ; ++i) cap[i] = 0;
     cap[1] = first;
@@ -157,18 +177,18 @@ struct BatchMatcher {
   }
 
   void reserve_level(int i, uint64_t rows) {
-    ws.rows[i].reserve(rows * 4 * (uint64_t)i);
-    ws.qid[i].reserve(rows * 2);
-    ws.W[i].reserve(rows * 4);
-    ws.apos[i].reserve(rows);
-    ws.abase[i].reserve(rows * 8);
-    ws.S[i].reserve((rows + 1) * 8);
+    ws.rows[i].reserve(rows * 4 * (uint64_t)i, s);
+    ws.qid[i].reserve(rows * 2, s);
+    ws.W[i].reserve(rows * 4, s);
+    ws.apos[i].reserve(rows, s);
+    ws.abase[i].reserve(rows * 8, s);
+    ws.S[i].reserve((rows + 1) * 8, s);
   }
 
   void evict_heavy(int i) {
     if (evict_pairs) {
-      ws.qpairs.reserve((nq + 1) * sizeof(uint64_t));
-      ws.evicted.reserve(nq + 1);
+      ws.qpairs.reserve((nq + 1) * sizeof(uint64_t), s);
+      ws.evicted.reserve(nq + 1, s);
       h_qpairs.resize(nq + 1);
       if (evicted.size() != (size_t)nq + 1) evicted.assign(nq + 1, 0);
       GSM_HIP(hipMemsetAsync(ws.qpairs.ptr, 0, (nq + 1) * sizeof(uint64_t), s));
@@ -271,7 +291,9 @@ struct BatchMatcher {
 }  // namespace
 
 void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_match_opts &o,
-                    Workspace &ws, uint64_t *counts, uint64_t *launches_out, gsm_stats *st) {
+                    Workspace &ws, uint64_t *counts, uint64_t *launches_out, gsm_stats *st,
+                    const RootSlice *slices) {
+    auto slice_of = [&](int k) { return slices ? slices[k] : RootSlice{}; };
     const hipStream_t stream = (hipStream_t)o.hip_stream;
     auto configure = [&](BatchMatcher &m) {
       m.rounds = o.filter_rounds;
@@ -289,13 +311,13 @@ void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_
     if (heavy_pairs == UINT64_MAX) {  // every query shares launches: nothing to estimate
       for (int k = 0; k < nq; ++k) light.push_back(k);
     } else {
-      BatchMatcher est(g, qs, nq, ws, stream);
+      BatchMatcher est(g, qs, nq, ws, stream, slices);
       configure(est);
       const std::vector<uint64_t> p1 = est.first_level_pairs();
       for (int k = 0; k < nq; ++k) (qs[k]->q > 1 && p1[k] > heavy_pairs ? heavy : light).push_back(k);
     }
     uint64_t launches = 0;
-    for (int k : heavy) counts[k] = match_count_one(g, *qs[k], o, ws);
+    for (int k : heavy) counts[k] = match_count_one(g, *qs[k], o, ws, slice_of(k));
     // the shared launches group queries of one size, so every level of a group
     // either writes the next frontier for all its rows or counts all of them
     for (int qsize = 1; qsize <= kMaxQ; ++qsize) {
@@ -304,9 +326,13 @@ void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_
         if (qs[k]->q == qsize) grp.push_back(k);
       if (grp.empty()) continue;
       std::vector<const gsm_query *> sub;
-      for (int k : grp) sub.push_back(qs[k]);
+      std::vector<RootSlice> sub_sl;
+      for (int k : grp) {
+        sub.push_back(qs[k]);
+        sub_sl.push_back(slice_of(k));
+      }
       std::vector<uint64_t> c(grp.size());
-      BatchMatcher m(g, sub.data(), (int)sub.size(), ws, stream);
+      BatchMatcher m(g, sub.data(), (int)sub.size(), ws, stream, sub_sl.data());
       configure(m);
       m.evict_pairs = heavy_pairs_opt == UINT64_MAX ? 0 : heavy_pairs_opt;
       m.plan_capacity();
@@ -318,7 +344,9 @@ void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_
           if (i > 0) st->rows[i - 1] += m.level_rows[i];
         }
       for (size_t j = 0; j < grp.size(); ++j)
-        counts[grp[j]] = (j < m.evicted.size() && m.evicted[j]) ? match_count_one(g, *qs[grp[j]], o, ws) : c[j];
+        counts[grp[j]] = (j < m.evicted.size() && m.evicted[j])
+                             ? match_count_one(g, *qs[grp[j]], o, ws, slice_of(grp[j]))
+                             : c[j];
     }
     if (launches_out) *launches_out = launches;
 }
@@ -357,9 +385,22 @@ extern "C" gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query
       gsm::set_error("gsm_match_batch: unique, induced, look-ahead and sorted modes are single-query options");
       return GSM_E_UNSUPPORTED;
     }
-    if (o.root_qvertex >= 0 || o.rows_on_device || o.emit) {
-      gsm::set_error("gsm_match_batch counts only: no root slice, rows or emit callback");
+    if (o.rows_on_device || o.emit) {
+      gsm::set_error("gsm_match_batch counts only: no rows or emit callback");
       return GSM_E_UNSUPPORTED;
+    }
+    std::vector<gsm::RootSlice> slices;
+    if (o.root_qvertex >= 0) {
+      if (o.root_mod == 0 || o.root_rem >= o.root_mod) {
+        gsm::set_error("gsm_match_batch: root slice needs root_rem < root_mod");
+        return GSM_E_INVALID_ARG;
+      }
+      for (int k = 0; k < nq; ++k)
+        if (o.root_qvertex >= qs[k]->q) {
+          gsm::set_error("gsm_match_batch: root_qvertex >= q of query " + std::to_string(k));
+          return GSM_E_INVALID_ARG;
+        }
+      slices.assign(nq, gsm::RootSlice{o.root_qvertex, o.root_mod, o.root_rem});
     }
     if (o.filter_rounds < 0 || o.filter_rounds > 64) throw Error{GSM_E_INVALID_ARG, "filter_rounds out of [0, 64]"};
     std::lock_guard<std::mutex> lk(g->mu);
@@ -367,7 +408,7 @@ extern "C" gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query
     uint64_t launches = 0;
     gsm_stats st;
     std::memset(&st, 0, sizeof(st));
-    gsm::match_batch_on(*g, qs, nq, o, *g->ws, counts, &launches, &st);
+    gsm::match_batch_on(*g, qs, nq, o, *g->ws, counts, &launches, &st, slices.empty() ? nullptr : slices.data());
     if (o.stats) {
       st.expand_launches = launches;
       const uint32_t sz = std::min<uint32_t>(o.stats->struct_size ? o.stats->struct_size : sizeof(gsm_stats),

@@ -20,15 +20,20 @@ namespace {
 std::atomic<int64_t> g_allocs_left{-1};
 }  // namespace
 
-void device_alloc(void **p, size_t bytes) {
+namespace {
+// one unit of the failure-injection allowance, or an injected failure
+void take_allocation() {
   int64_t left = g_allocs_left.load();
   while (left >= 0) {
-    if (left == 0) {
-      *p = nullptr;
-      throw Error{GSM_E_OOM, "device allocation refused (failure injection)"};
-    }
+    if (left == 0) throw Error{GSM_E_OOM, "device allocation refused (failure injection)"};
     if (g_allocs_left.compare_exchange_weak(left, left - 1)) break;
   }
+}
+}  // namespace
+
+void device_alloc(void **p, size_t bytes) {
+  *p = nullptr;
+  take_allocation();
   if (hipMalloc(p, bytes) != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
@@ -36,20 +41,42 @@ void device_alloc(void **p, size_t bytes) {
   }
 }
 
-void DevBuf::reserve(size_t want) {
-  if (want <= bytes && ptr) return;
-  if (ptr) (void)hipDeviceSynchronize();  // no pending kernel may still use the old buffer
-  release();
-  if (want == 0) return;
-  const size_t b = (want + 255) & ~size_t(255);
-  device_alloc(&ptr, b);
-  bytes = b;
+void device_alloc_async(void **p, size_t bytes, hipStream_t s) {
+  *p = nullptr;
+  take_allocation();
+  if (hipMallocAsync(p, bytes, s) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    throw Error{GSM_E_OOM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed"};
+  }
 }
 
-void DevBuf::release() {
-  if (ptr) (void)hipFree(ptr);
+void DevBuf::reserve(size_t want, hipStream_t s) {
+  if (want <= bytes && ptr) return;
+  if (fixed) {
+    if (want == 0) return;
+    throw Error{GSM_E_BUDGET, "no-allocation scratch: a buffer of " + std::to_string(want) +
+                                  " bytes does not fit its window of " + std::to_string(bytes)};
+  }
+  release(s);  // stream-ordered: the old block is freed after the stream's earlier work
+  if (want == 0) return;
+  const size_t b = (want + 255) & ~size_t(255);
+  device_alloc_async(&ptr, b, s);
+  bytes = b;
+  pooled = true;
+}
+
+void DevBuf::release(hipStream_t s) {
+  if (ptr && !fixed) {
+    if (pooled)
+      (void)hipFreeAsync(ptr, s);
+    else
+      (void)hipFree(ptr);
+  }
   ptr = nullptr;
   bytes = 0;
+  fixed = false;
+  pooled = false;
 }
 
 // Label-grouped copy of the adjacency: each row stably partitioned by
@@ -96,14 +123,28 @@ void build_edge_label_table(gsm_graph &g, const int64_t *rp, const int32_t *col,
 }
 
 Workspace::Workspace() {
-  counters.reserve(64 * sizeof(uint64_t));
-  scan_scratch.reserve(scan_scratch_elems() * sizeof(uint64_t));
+  counters.reserve(64 * sizeof(uint64_t), nullptr);
+  scan_scratch.reserve(scan_scratch_elems() * sizeof(uint64_t), nullptr);
   GSM_HIP(hipHostMalloc((void **)&h_counters, 64 * sizeof(uint64_t), hipHostMallocDefault));
   std::memset(h_counters, 0, 64 * sizeof(uint64_t));
 }
 
+size_t Workspace::fixed_header_bytes() {
+  return 64 * sizeof(uint64_t) + ((scan_scratch_elems() * sizeof(uint64_t) + 255) & ~size_t(255));
+}
+
+Workspace::Workspace(void *base, size_t bytes) {
+  fixed_base = static_cast<char *>(base);
+  fixed_bytes = bytes;
+  if (bytes < fixed_header_bytes()) throw Error{GSM_E_BUDGET, "no-allocation scratch below its header"};
+  counters.set_fixed(fixed_base, 64 * sizeof(uint64_t));
+  scan_scratch.set_fixed(fixed_base + 64 * sizeof(uint64_t), fixed_header_bytes() - 64 * sizeof(uint64_t));
+  h_counters = h_local;
+  std::memset(h_local, 0, sizeof(h_local));
+}
+
 Workspace::~Workspace() {
-  if (h_counters) (void)hipHostFree(h_counters);
+  if (h_counters && h_counters != h_local) (void)hipHostFree(h_counters);
   for (auto &e : events) (void)hipEventDestroy(e);
 }
 

@@ -37,12 +37,29 @@ struct Error {
 // hipMalloc that throws Error{GSM_E_OOM} on failure (and when the test hook
 // gsm_testing_fail_allocations has used up its allowance).
 void device_alloc(void **p, size_t bytes);
+// The same, stream-ordered (hipMallocAsync on s): no device-wide wait.
+void device_alloc_async(void **p, size_t bytes, hipStream_t s);
 
+// A device buffer owned by one workspace.  Growing it frees the old block
+// and allocates the new one in the order of the stream that uses it
+// (hipFreeAsync / hipMallocAsync), so a workspace that grows waits for its
+// own stream's work only, never for other streams on the device.
+// A fixed buffer is a window of memory the library does not own (the
+// no-allocation scratch): it never allocates or frees, and asking it for more
+// than its size is a GSM_E_BUDGET error.
 struct DevBuf {
   void *ptr = nullptr;
   size_t bytes = 0;
-  void reserve(size_t want);  // keeps no contents
-  void release();
+  bool fixed = false;
+  bool pooled = false;  // from hipMallocAsync: always returned with hipFreeAsync
+  void reserve(size_t want, hipStream_t s);  // keeps no contents
+  void release(hipStream_t s = nullptr);     // s: free in that stream's order
+  void set_fixed(void *p, size_t b) {
+    release();
+    ptr = p;
+    bytes = b;
+    fixed = true;
+  }
   template <typename T>
   T *as() const { return static_cast<T *>(ptr); }
   ~DevBuf() { release(); }
@@ -205,6 +222,8 @@ void launch_compact_first(const DeviceGraph &g, const uint16_t *cmask, uint32_t 
 void build_label_table(gsm_graph &g, const int64_t *h_rp, const int32_t *h_col, const int32_t *h_lab);
 // S[0..N] = exclusive scan of W[0..N-1]; N read from device *n_dev; scratch >= scan_scratch_bytes()
 size_t scan_scratch_elems();
+// p[0..count) = 0 with a kernel (no memset node, so a captured stream replays it correctly)
+void launch_zero_u64(uint64_t *p, size_t count, hipStream_t s);
 void launch_scan(const uint32_t *W, const uint64_t *n_dev, uint64_t *S, uint64_t *total_out,
                  uint64_t *scratch, hipStream_t s);
 
@@ -226,6 +245,16 @@ struct BatchLevel {
   uint64_t qne;            // NE of position i's query vertex (0 = no test)
   uint32_t qdeg;           // degree of position i's query vertex (0 = no test)
   int32_t qlab;            // label of position i's query vertex
+  // root slice on position i's query vertex: keep w with
+  // splitmix64(w) % slice_mod == slice_rem (slice_mod 0 = no slice)
+  uint32_t slice_mod, slice_rem;
+};
+
+// Root slice of one query (the gsm_match_opts convention): keep embeddings
+// with splitmix64(f(qvertex)) % mod == rem; qvertex < 0 = the whole query.
+struct RootSlice {
+  int32_t qvertex = -1;
+  uint32_t mod = 1, rem = 0;
 };
 
 struct ExpandArgs {
@@ -279,19 +308,31 @@ struct FirstBatch {
   int32_t qlab0;      // position 0: label
   int32_t label1;     // label of position 1 (unused when q == 1)
   int32_t single;     // q == 1
+  uint32_t slice_mod, slice_rem;  // root slice on position 0 (slice_mod 0 = none)
 };
 void launch_compact_first_batch(const DeviceGraph &g, const FirstBatch *fb_dev,
                                 int nq, int32_t *rows, uint16_t *qid, uint32_t *W, int64_t *abase,
                                 uint8_t *apos, uint64_t *counter, uint64_t *counts, uint64_t *pairs1,
                                 hipStream_t s);
-// Count-only match of one query on the workspace (the single-query driver).
-uint64_t match_count_one(gsm_graph &g, const gsm_query &q, const gsm_match_opts &o, Workspace &ws);
+// The single-query entry: gsm_match (fixed_ws = null: the graph's workspace,
+// under its lock) or gsm_match_noalloc (a fixed workspace over the
+// no-allocation scratch).
+gsm_status match_call(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, uint64_t *count,
+                      int32_t *rows, uint64_t rows_cap, uint64_t *rows_written, Workspace *fixed_ws);
+// Count-only match of one query on the workspace (the single-query driver),
+// restricted to the root slice rs.
+uint64_t match_count_one(gsm_graph &g, const gsm_query &q, const gsm_match_opts &o, Workspace &ws,
+                         const RootSlice &rs);
+// Smallest budget gsm_match accepts for a query of q vertices, count only.
+uint64_t min_budget_bytes_single(int64_t n, int q);
 // Smallest batched budget for nq queries of q vertices (first frontiers at
 // n rows each, one row per further level).
 uint64_t min_budget_bytes_batch(const gsm_graph &g, int nq, int q);
-// Counts of a set of queries on the workspace (the batched driver, no locking).
+// Counts of a set of queries on the workspace (the batched driver, no
+// locking); slices: one root slice per query, or null for none.
 void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_match_opts &o,
-                    Workspace &ws, uint64_t *counts, uint64_t *launches, gsm_stats *st);
+                    Workspace &ws, uint64_t *counts, uint64_t *launches, gsm_stats *st,
+                    const RootSlice *slices);
 
 // -------------------------------------------------------------- workspace --
 
@@ -317,10 +358,20 @@ struct Workspace {
   DevBuf counters;  // kMaxQ + 8 uint64
   DevBuf scan_scratch;
   DevBuf emit;      // staging for host-bound rows
-  uint64_t *h_counters = nullptr;  // pinned host mirror
+  uint64_t *h_counters = nullptr;  // pinned host mirror (a plain host array in a fixed workspace)
   std::vector<hipEvent_t> events;  // profiling event pool
+  // Fixed workspace (no device allocation): every buffer is a window of
+  // [fixed_base, fixed_base + fixed_bytes); counters and scan scratch sit at
+  // its start, the rest is laid out per call once the level capacities are
+  // known.
+  char *fixed_base = nullptr;
+  size_t fixed_bytes = 0;
+  uint64_t h_local[64];
   Workspace();
+  Workspace(void *base, size_t bytes);  // fixed
   ~Workspace();
+  // bytes at the start of a fixed workspace taken by counters and scan scratch
+  static size_t fixed_header_bytes();
 };
 
 }  // namespace gsm

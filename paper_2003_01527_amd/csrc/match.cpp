@@ -149,16 +149,17 @@ struct Matcher {
 
   // Filter into ws.cmask (query-id bits).
   void filter() {
-    ws.cmask.reserve(std::max<int64_t>(g.n, 1) * sizeof(uint16_t));
+    ws.cmask.reserve(std::max<int64_t>(g.n, 1) * sizeof(uint16_t), s);
     const QueryArgs qa = query_args();
     launch_filter_init(dg, qa, ws.cmask.as<uint16_t>(), s);
     st.filter_bytes += (uint64_t)g.n * (4 + 4 + (g.ne0 ? 8 : 0) + 2);
-    if (o.rounds > 0) ws.cmask2.reserve(std::max<int64_t>(g.n, 1) * sizeof(uint16_t));
+    if (o.rounds > 0) ws.cmask2.reserve(std::max<int64_t>(g.n, 1) * sizeof(uint16_t), s);
     for (int r = 0; r < o.rounds; ++r) {
       launch_filter_refine(dg, g.heavy, g.nheavy, qa, ws.cmask.as<uint16_t>(),
                            ws.cmask2.as<uint16_t>(), s);
       std::swap(ws.cmask.ptr, ws.cmask2.ptr);
       std::swap(ws.cmask.bytes, ws.cmask2.bytes);
+      std::swap(ws.cmask.pooled, ws.cmask2.pooled);
       st.filter_bytes += (uint64_t)(g.n + 1) * 8 + (uint64_t)g.nnz * (4 + 2 + (g.lab ? 4 : 0)) +
                          (uint64_t)g.n * 4;
     }
@@ -171,9 +172,7 @@ struct Matcher {
     sync();
   }
 
-  void zero_counter(int slot) {
-    GSM_HIP(hipMemsetAsync(dcnt + slot, 0, sizeof(uint64_t), s));
-  }
+  void zero_counter(int slot) { launch_zero_u64(dcnt + slot, 1, s); }
 
   std::pair<hipEvent_t, hipEvent_t> next_events() {
     while (ws.events.size() < 2 * (ev_next + 1)) {
@@ -220,29 +219,66 @@ struct Matcher {
       staged_cap = std::min<uint64_t>(rest / shares / (uint64_t)(4 * p.q), uint64_t(1) << 26);
       if (staged_cap < 1) throw Error{GSM_E_BUDGET, "memory budget below one output row"};
     }
+    if (ws.fixed_base) {
+      carve_fixed();
+      return;
+    }
     // Buffers are kept across calls (reallocation costs milliseconds); when
     // what earlier calls left behind exceeds this call's budget, start over.
-    uint64_t held = ws.cmask.bytes + ws.cmask2.bytes + ws.emit.bytes;
+    // (buffers a batched call left in the same workspace count too)
+    uint64_t held = ws.cmask.bytes + ws.cmask2.bytes + ws.emit.bytes + ws.tables.bytes + ws.counts.bytes +
+                    ws.qpairs.bytes + ws.evicted.bytes;
     for (int i = 0; i < kMaxQ; ++i)
-      held += ws.rows[i].bytes + ws.S[i].bytes + ws.W[i].bytes + ws.apos[i].bytes + ws.abase[i].bytes;
+      held += ws.rows[i].bytes + ws.S[i].bytes + ws.W[i].bytes + ws.apos[i].bytes + ws.abase[i].bytes +
+              ws.qid[i].bytes;
     if (held > o.budget) {
       for (int i = 2; i < kMaxQ; ++i) {
-        ws.rows[i].release();
-        ws.S[i].release();
-        ws.W[i].release();
-        ws.apos[i].release();
-        ws.abase[i].release();
+        ws.rows[i].release(s);
+        ws.S[i].release(s);
+        ws.W[i].release(s);
+        ws.apos[i].release(s);
+        ws.abase[i].release(s);
       }
-      ws.emit.release();
+      for (int i = 0; i < kMaxQ; ++i) ws.qid[i].release(s);
+      ws.emit.release(s);
+      ws.qpairs.release(s);
+      ws.evicted.release(s);
     }
   }
 
+  // A fixed workspace: lay every buffer of this call out in the window after
+  // the counters, at the capacities plan_capacity chose.
+  void carve_fixed() {
+    char *base = ws.fixed_base + Workspace::fixed_header_bytes();
+    const char *end = ws.fixed_base + ws.fixed_bytes;
+    auto take = [&](DevBuf &b, uint64_t want) {
+      const uint64_t sz = (std::max<uint64_t>(want, 1) + 255) & ~uint64_t(255);
+      if (sz > (uint64_t)(end - base))
+        throw Error{GSM_E_BUDGET, "no-allocation scratch of " + std::to_string(ws.fixed_bytes) +
+                                      " bytes too small for this graph and query"};
+      b.set_fixed(base, sz);
+      base += sz;
+    };
+    const uint64_t n = (uint64_t)std::max<int64_t>(g.n, 1);
+    take(ws.cmask, n * 2);
+    take(ws.cmask2, n * 2);
+    for (int i = 1; i < p.q; ++i) {
+      const uint64_t c = cap[i];
+      take(ws.rows[i], c * 4 * (uint64_t)i);
+      take(ws.W[i], c * 4);
+      take(ws.apos[i], c);
+      take(ws.abase[i], c * 8);
+      take(ws.S[i], (c + 1) * 8);
+    }
+    if (emit_host) take(ws.emit, p.q == 1 ? n * 4 : staged_cap * (uint64_t)p.q * 4);
+  }
+
   void reserve_level(int i, uint64_t rows) {
-    ws.rows[i].reserve(rows * 4 * (uint64_t)i);
-    ws.W[i].reserve(rows * 4);
-    ws.apos[i].reserve(rows);
-    ws.abase[i].reserve(rows * 8);
-    ws.S[i].reserve((rows + 1) * 8);
+    ws.rows[i].reserve(rows * 4 * (uint64_t)i, s);
+    ws.W[i].reserve(rows * 4, s);
+    ws.apos[i].reserve(rows, s);
+    ws.abase[i].reserve(rows * 8, s);
+    ws.S[i].reserve((rows + 1) * 8, s);
   }
 
   LevelArgs level_args(int i) const {
@@ -368,7 +404,7 @@ struct Matcher {
       expand(a, kModeEmit);
       st.chunks[i]++;
     } else {  // through the staging buffer, one chunk at a time
-      ws.emit.reserve(std::min(staged_cap, P) * p.q * sizeof(int32_t));
+      ws.emit.reserve(std::min(staged_cap, P) * p.q * sizeof(int32_t), s);
       for (uint64_t b = 0; b < P && !cancelled; b += staged_cap) {
         const uint64_t e = std::min(P, b + staged_cap);
         a.pair_begin = b;
@@ -385,7 +421,7 @@ struct Matcher {
   }
 
   uint64_t run() {
-    GSM_HIP(hipMemsetAsync(dcnt, 0, 64 * sizeof(uint64_t), s));
+    launch_zero_u64(dcnt, 64, s);
     filter();
     const int q = p.q;
     const uint32_t qbit0 = (uint32_t)p.order[0];
@@ -398,7 +434,7 @@ struct Matcher {
           dst = rows_user;
           dcap = rows_cap;
         } else {
-          ws.emit.reserve(std::max<int64_t>(g.n, 1) * sizeof(int32_t));
+          ws.emit.reserve(std::max<int64_t>(g.n, 1) * sizeof(int32_t), s);
           dst = ws.emit.as<int32_t>();
           dcap = (uint64_t)g.n;
         }
@@ -457,7 +493,7 @@ void sort_rows(int32_t *rows, uint64_t N, int q, int64_t n, bool on_device, Sort
     sort_rows_device(rows, N, q, n, sb, s);
   } else {
     const size_t bytes = sizeof(int32_t) * q * N;
-    sb.rows.reserve(bytes);
+    sb.rows.reserve(bytes, s);
     GSM_HIP(hipMemcpyAsync(sb.rows.ptr, rows, bytes, hipMemcpyHostToDevice, s));
     sort_rows_device(sb.rows.as<int32_t>(), N, q, n, sb, s);
     GSM_HIP(hipMemcpyAsync(rows, sb.rows.ptr, bytes, hipMemcpyDeviceToHost, s));
@@ -472,18 +508,99 @@ Workspace &acquire_ws(gsm_graph &g) {
 
 }  // namespace
 
-uint64_t match_count_one(gsm_graph &g, const gsm_query &q, const gsm_match_opts &oo, Workspace &ws) {
-  Options o = read_opts(&oo, q.q);
+uint64_t min_budget_bytes_single(int64_t n, int q) { return min_budget_bytes(n, q, false); }
+
+uint64_t match_count_one(gsm_graph &g, const gsm_query &q, const gsm_match_opts &oo, Workspace &ws,
+                         const RootSlice &rs) {
+  gsm_match_opts plain = oo;
+  plain.root_qvertex = rs.qvertex;
+  plain.root_mod = rs.qvertex >= 0 ? rs.mod : 0;
+  plain.root_rem = rs.qvertex >= 0 ? rs.rem : 0;
+  Options o = read_opts(&plain, q.q);
   o.emit = nullptr;
   o.emit_ctx = nullptr;
   o.rows_dev = false;
   o.stats = nullptr;
-  o.root_q = -1;
   Matcher m(g, q, o, ws);
   m.plan_capacity();
   const uint64_t c = m.run();
   m.sync();
   return c;
+}
+
+// The body of gsm_match.  fixed_ws != null: the no-allocation variant, on a
+// fixed workspace (no graph lock, no device allocation, no sort, no events).
+gsm_status match_call(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, uint64_t *count,
+                      int32_t *rows, uint64_t rows_cap, uint64_t *rows_written, Workspace *fixed_ws) {
+  const auto t0 = std::chrono::steady_clock::now();
+  try {
+    if (!g || !qh || !count) {
+      set_error(fixed_ws ? "gsm_match_noalloc: NULL argument" : "gsm_match: NULL argument");
+      return GSM_E_INVALID_ARG;
+    }
+    Options o = read_opts(opts, qh->q);
+    if (o.sort && o.emit) {
+      set_error("GSM_MATCH_SORT_ROWS needs the rows buffer, not an emit callback");
+      return GSM_E_UNSUPPORTED;
+    }
+    std::unique_lock<std::mutex> lk(g->mu, std::defer_lock);
+    Workspace *wsp = fixed_ws;
+    if (fixed_ws) {
+      if (o.sort) {
+        set_error("gsm_match_noalloc: GSM_MATCH_SORT_ROWS needs sort buffers; sort with gsm_sort_rows");
+        return GSM_E_UNSUPPORTED;
+      }
+      o.profile = false;  // no event objects are created
+      // the level budget is what the scratch holds after its header, minus
+      // the alignment of each window
+      const uint64_t room = fixed_ws->fixed_bytes - Workspace::fixed_header_bytes() - (uint64_t(24) << 10);
+      if (fixed_bytes(g->n) + 64 > room) {
+        set_error("gsm_match_noalloc: a graph of " + std::to_string(g->n) + " vertices needs " +
+                  std::to_string(fixed_bytes(g->n) + 64) + " bytes of scratch for its candidate masks and "
+                  "first frontier; the no-allocation scratch holds " + std::to_string(room));
+        return GSM_E_BUDGET;
+      }
+      o.budget = std::min<uint64_t>(o.budget, room);
+    } else {
+      lk.lock();
+      wsp = &acquire_ws(*g);
+    }
+    Workspace &ws = *wsp;
+    Matcher m(*g, *qh, o, ws);
+    m.rows_user = rows;
+    m.rows_cap = rows ? rows_cap : 0;
+    m.emit_host = (o.emit != nullptr) || (rows != nullptr && !o.rows_dev);
+    m.plan_capacity();
+    const uint64_t c = m.run();
+    m.sync();
+    m.finish_stats(c);
+    *count = c;
+    const uint64_t written = rows ? std::min(c, rows_cap) : 0;
+    if (o.sort && written > 1) sort_rows(rows, written, qh->q, g->n, o.rows_dev, ws.sort, m.s);
+    if (rows_written) *rows_written = written;
+    if (o.stats) {
+      m.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      const uint32_t sz = std::min<uint32_t>(o.stats->struct_size ? o.stats->struct_size : sizeof(gsm_stats),
+                                             sizeof(gsm_stats));
+      std::memcpy(o.stats, &m.st, sz);
+      o.stats->struct_size = sz;
+    }
+    if (m.cancelled) {
+      set_error("emit callback stopped the match");
+      return GSM_E_CANCELLED;
+    }
+    if (rows && c > rows_cap) {
+      set_error("count exceeds rows_cap; first rows_cap rows written");
+      return GSM_E_TRUNCATED;
+    }
+    return GSM_OK;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc &) {
+    set_error("host allocation failed");
+    return GSM_E_OOM;
+  }
 }
 
 }  // namespace gsm
@@ -528,54 +645,7 @@ gsm_status gsm_filter(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts,
 
 gsm_status gsm_match(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, uint64_t *count,
                      int32_t *rows, uint64_t rows_cap, uint64_t *rows_written) {
-  const auto t0 = std::chrono::steady_clock::now();
-  try {
-    if (!g || !qh || !count) {
-      gsm::set_error("gsm_match: NULL argument");
-      return GSM_E_INVALID_ARG;
-    }
-    const gsm::Options o = gsm::read_opts(opts, qh->q);
-    if (o.sort && o.emit) {
-      gsm::set_error("GSM_MATCH_SORT_ROWS needs the rows buffer, not an emit callback");
-      return GSM_E_UNSUPPORTED;
-    }
-    std::lock_guard<std::mutex> lk(g->mu);
-    gsm::Workspace &ws = gsm::acquire_ws(*g);
-    gsm::Matcher m(*g, *qh, o, ws);
-    m.rows_user = rows;
-    m.rows_cap = rows ? rows_cap : 0;
-    m.emit_host = (o.emit != nullptr) || (rows != nullptr && !o.rows_dev);
-    m.plan_capacity();
-    const uint64_t c = m.run();
-    m.sync();
-    m.finish_stats(c);
-    *count = c;
-    const uint64_t written = rows ? std::min(c, rows_cap) : 0;
-    if (o.sort && written > 1) gsm::sort_rows(rows, written, qh->q, g->n, o.rows_dev, ws.sort, m.s);
-    if (rows_written) *rows_written = written;
-    if (o.stats) {
-      m.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-      const uint32_t sz = std::min<uint32_t>(o.stats->struct_size ? o.stats->struct_size : sizeof(gsm_stats),
-                                             sizeof(gsm_stats));
-      std::memcpy(o.stats, &m.st, sz);
-      o.stats->struct_size = sz;
-    }
-    if (m.cancelled) {
-      gsm::set_error("emit callback stopped the match");
-      return GSM_E_CANCELLED;
-    }
-    if (rows && c > rows_cap) {
-      gsm::set_error("count exceeds rows_cap; first rows_cap rows written");
-      return GSM_E_TRUNCATED;
-    }
-    return GSM_OK;
-  } catch (const Error &e) {
-    gsm::set_error(e.msg);
-    return e.status;
-  } catch (const std::bad_alloc &) {
-    gsm::set_error("host allocation failed");
-    return GSM_E_OOM;
-  }
+  return gsm::match_call(g, qh, opts, count, rows, rows_cap, rows_written, nullptr);
 }
 
 gsm_status gsm_sort_rows(gsm_graph_t g, int32_t *rows, uint64_t nrows, int32_t q, int32_t rows_on_device,

@@ -23,6 +23,7 @@ uint64_t now_ns() {
 struct Request {
   uint64_t ticket;
   gsm_query q;       // private copy
+  gsm::RootSlice slice;
   uint64_t reserve;  // admitted bytes
   gsm_result res;
   bool done = false;
@@ -53,9 +54,19 @@ struct gsm_server {
     const int32_t l0 = p.qlab[p.order[0]];
     const uint64_t pairs = (l0 >= 0 && (size_t)l0 < label_deg.size()) ? label_deg[l0] : 0;
     const uint64_t row2 = 4 * 2 + 23;
-    uint64_t est = pairs * row2 + gsm::min_budget_bytes_batch(*g, 1, p.q);
-    est = std::max<uint64_t>(est, gsm::min_budget_bytes_batch(*g, 1, p.q) + (uint64_t(64) << 20));
-    return std::min<uint64_t>(est, o.per_query_budget);
+    // the smallest budget either driver accepts for this query alone (a batch
+    // of one, or the single-query path a heavy query is moved to)
+    const uint64_t floor = std::max(gsm::min_budget_bytes_batch(*g, 1, p.q), gsm::min_budget_bytes_single(g->n, p.q));
+    uint64_t est = pairs * row2 + floor;
+    est = std::max<uint64_t>(est, floor + (uint64_t(64) << 20));
+    return std::max(floor, std::min<uint64_t>(est, o.per_query_budget));
+  }
+
+  // the oldest waiting request fits now (caller holds mu)
+  bool admissible() const {
+    if (pending.empty() || active >= o.max_active) return false;
+    const Request *r = pending.front();
+    return reserved + r->reserve <= o.arena_bytes || reserved == 0;  // an oversize query runs alone
   }
 
   void worker_main(int wid) {
@@ -74,13 +85,14 @@ struct gsm_server {
       uint64_t budget = 0;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stopping || !pending.empty(); });
+        // sleep until the oldest waiting request can be admitted (it fits the
+        // free arena, or nothing is running so it may run alone, and a slot
+        // is free) or the server stops; a finishing batch wakes the workers
+        cv_work.wait(lk, [&] { return (stopping && pending.empty()) || admissible(); });
         if (pending.empty() && stopping) break;
         // admit the oldest requests that fit the free arena
-        while (!pending.empty() && (int)batch.size() < o.max_batch && active < o.max_active) {
+        while (!pending.empty() && (int)batch.size() < o.max_batch && admissible()) {
           Request *r = pending.front();
-          const bool fits = reserved + r->reserve <= o.arena_bytes;
-          if (!fits && !(batch.empty() && reserved == 0)) break;  // an oversize query runs alone
           pending.pop_front();
           reserved += r->reserve;
           budget += r->reserve;
@@ -88,10 +100,13 @@ struct gsm_server {
           r->res.t_admit_ns = now_ns();
           batch.push_back(r);
         }
-        if (batch.empty()) continue;  // memory frees up when a running batch ends
       }
       std::vector<const gsm_query *> qs;
-      for (Request *r : batch) qs.push_back(&r->q);
+      std::vector<gsm::RootSlice> slices;
+      for (Request *r : batch) {
+        qs.push_back(&r->q);
+        slices.push_back(r->slice);
+      }
       std::vector<uint64_t> counts(batch.size(), 0);
       gsm_status st = GSM_OK;
       std::string err;
@@ -103,7 +118,8 @@ struct gsm_server {
         mo.wg_size = o.wg_size;
         mo.tile_items = o.tile_items;
         mo.batch_heavy_pairs = o.batch_heavy_pairs;
-        gsm::match_batch_on(*g, qs.data(), (int)qs.size(), mo, *ws, counts.data(), nullptr, nullptr);
+        gsm::match_batch_on(*g, qs.data(), (int)qs.size(), mo, *ws, counts.data(), nullptr, nullptr,
+                            slices.data());
       } catch (const gsm::Error &e) {
         st = e.status;
         err = e.msg;
@@ -198,7 +214,8 @@ gsm_status gsm_server_create(gsm_graph_t g, const gsm_server_opts *opts, gsm_ser
   return GSM_OK;
 }
 
-gsm_status gsm_server_submit(gsm_server_t srv, gsm_query_t qh, uint64_t *ticket) {
+gsm_status gsm_server_submit_slice(gsm_server_t srv, gsm_query_t qh, int32_t root_qvertex, uint32_t root_mod,
+                                   uint32_t root_rem, uint64_t *ticket) {
   if (!srv || !qh || !ticket) {
     gsm::set_error("gsm_server_submit: NULL argument");
     return GSM_E_INVALID_ARG;
@@ -207,8 +224,13 @@ gsm_status gsm_server_submit(gsm_server_t srv, gsm_query_t qh, uint64_t *ticket)
     gsm::set_error("gsm_server_submit: edge-labelled queries are matched one at a time (gsm_match)");
     return GSM_E_UNSUPPORTED;
   }
+  if (root_qvertex >= 0 && (root_qvertex >= qh->q || root_mod == 0 || root_rem >= root_mod)) {
+    gsm::set_error("gsm_server_submit_slice: root_qvertex < q and root_rem < root_mod required");
+    return GSM_E_INVALID_ARG;
+  }
   auto r = new Request();
   r->q = *qh;
+  if (root_qvertex >= 0) r->slice = gsm::RootSlice{root_qvertex, root_mod, root_rem};
   std::memset(&r->res, 0, sizeof(r->res));
   r->res.t_submit_ns = now_ns();
   try {
@@ -232,6 +254,10 @@ gsm_status gsm_server_submit(gsm_server_t srv, gsm_query_t qh, uint64_t *ticket)
   }
   srv->cv_work.notify_one();
   return GSM_OK;
+}
+
+gsm_status gsm_server_submit(gsm_server_t srv, gsm_query_t qh, uint64_t *ticket) {
+  return gsm_server_submit_slice(srv, qh, -1, 0, 0, ticket);
 }
 
 gsm_status gsm_server_wait(gsm_server_t srv, uint64_t ticket, int32_t timeout_ms, gsm_result *out) {

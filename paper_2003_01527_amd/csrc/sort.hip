@@ -150,12 +150,12 @@ void sort_rows_device(int32_t *rows, uint64_t N, int q, int64_t n, SortBuffers &
   const int bits = b * q;
   const int W = (bits + 63) / 64;
   const uint64_t tiles = (N + kSortTile - 1) / kSortTile;
-  sb.keys[0].reserve(sizeof(uint64_t) * W * N);
-  sb.keys[1].reserve(sizeof(uint64_t) * W * N);
-  sb.hist.reserve(sizeof(uint32_t) * kDigits * tiles);
-  sb.offs.reserve(sizeof(uint64_t) * (kDigits * tiles + 1));
-  sb.len.reserve(sizeof(uint64_t));
-  sb.scratch.reserve(sizeof(uint64_t) * 1024);
+  sb.keys[0].reserve(sizeof(uint64_t) * W * N, s);
+  sb.keys[1].reserve(sizeof(uint64_t) * W * N, s);
+  sb.hist.reserve(sizeof(uint32_t) * kDigits * tiles, s);
+  sb.offs.reserve(sizeof(uint64_t) * (kDigits * tiles + 1), s);
+  sb.len.reserve(sizeof(uint64_t), s);
+  sb.scratch.reserve(sizeof(uint64_t) * 1024, s);
   uint64_t *k0 = sb.keys[0].as<uint64_t>(), *k1 = sb.keys[1].as<uint64_t>();
   const unsigned grid = (unsigned)std::min<uint64_t>((N + 255) / 256, 65536);
   hipLaunchKernelGGL(k_sort_pack, dim3(grid), dim3(256), 0, s, rows, N, q, b, W, k0);

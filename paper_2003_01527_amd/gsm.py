@@ -126,6 +126,8 @@ def _load():
     lib.gsm_server_create.argtypes = [vp, P(ServerOpts), P(vp)]
     lib.gsm_server_submit.restype = ctypes.c_int
     lib.gsm_server_submit.argtypes = [vp, vp, P(u64)]
+    lib.gsm_server_submit_slice.restype = ctypes.c_int
+    lib.gsm_server_submit_slice.argtypes = [vp, vp, i32, u32, u32, P(u64)]
     lib.gsm_server_wait.restype = ctypes.c_int
     lib.gsm_server_wait.argtypes = [vp, u64, i32, P(Result)]
     lib.gsm_server_destroy.argtypes = [vp]
@@ -280,6 +282,10 @@ def match(graph: Graph, query: Query, rows=None, rows_cap: Optional[int] = None,
     per output chunk, rows left in device memory.  A callback returning a true
     value stops the match.  Returns (count, rows_or_None, stats dict).
     """
+    return _match("gsm_match", graph, query, rows, rows_cap, emit, emit_device, **kw)
+
+
+def _match(entry: str, graph: Graph, query: Query, rows, rows_cap, emit, emit_device, **kw):
     lib = _load()
     st = Stats()
     o = make_opts(stats=st, **kw)
@@ -316,8 +322,8 @@ def match(graph: Graph, query: Query, rows=None, rows_cap: Optional[int] = None,
         if o.hip_stream is None:
             import torch
             o.hip_stream = ctypes.c_void_p(torch.cuda.current_stream(rows.device).cuda_stream)
-    status = lib.gsm_match(graph._h, query._h, ctypes.byref(o), ctypes.byref(cnt), ptr, cap,
-                           ctypes.byref(written))
+    status = getattr(lib, entry)(graph._h, query._h, ctypes.byref(o), ctypes.byref(cnt), ptr, cap,
+                                 ctypes.byref(written))
     _check(status, allow=(7,))
     count = int(cnt.value)
     if isinstance(out, np.ndarray):
@@ -355,9 +361,14 @@ class Server:
         self._h = ctypes.c_void_p()
         _check(lib.gsm_server_create(graph._h, ctypes.byref(o), ctypes.byref(self._h)))
 
-    def submit(self, query: Query) -> int:
+    def submit(self, query: Query, root=None) -> int:
+        """root: (query vertex, mod, rem) slice, or None for the whole query."""
         t = ctypes.c_uint64()
-        _check(_load().gsm_server_submit(self._h, query._h, ctypes.byref(t)))
+        if root is None:
+            _check(_load().gsm_server_submit(self._h, query._h, ctypes.byref(t)))
+        else:
+            _check(_load().gsm_server_submit_slice(self._h, query._h, int(root[0]), int(root[1]), int(root[2]),
+                                                   ctypes.byref(t)))
         return int(t.value)
 
     def wait(self, ticket: int, timeout_ms: int = -1) -> dict:

@@ -1,0 +1,102 @@
+"""Batched, served and large-graph counts against the oracle on fixed root
+slices, through the C ABI.
+
+The expected counts are the oracle's (tests/golden/*_slice_counts.txt,
+written by tests/golden/make_slice_counts.py, which calls only oracle/ and
+the seeded generators); each file carries a fingerprint of its workload,
+checked first so a changed generator is not mistaken for a wrong count.
+Tolerance zero: the work is integer.
+"""
+import numpy as np
+import pytest
+
+from paper_2003_01527_amd import gsm
+from paper_2003_01527_amd import workloads as W
+
+from golden.make_slice_counts import (BATCH_SLICE, LARGE_MOD, SERVING_ARRIVALS, SERVING_MOD,
+                                      fingerprint)
+from golden_io import GOLDEN
+
+pytestmark = pytest.mark.gpu
+
+
+def golden(fname):
+    fp, rows = None, []
+    for line in open(GOLDEN + "/" + fname):
+        if line.startswith("# fingerprint"):
+            fp = line.split()[2]
+        elif not line.startswith("#") and line.strip():
+            rows.append(line.split())
+    return fp, rows
+
+
+@pytest.fixture(scope="module")
+def batch_workload():
+    w = W.batch()
+    fp, rows = golden("batch_slice_counts.txt")
+    assert fingerprint(w.graph, w.queries) == fp, "batching workload differs from the one the counts were taken on"
+    expect = np.array([int(r[1]) for r in rows], dtype=np.uint64)
+    assert expect.shape[0] == len(w.queries)
+    return w, gsm.Graph.from_workload(w.graph), [gsm.Query.from_workload(q) for q in w.queries], expect
+
+
+@pytest.mark.parametrize("heavy", ["default", "all_shared", "all_alone"])
+def test_batch_all_queries_on_slice_equal_oracle(batch_workload, heavy):
+    w, G, Qs, expect = batch_workload
+    hp = {"default": 0, "all_shared": (1 << 64) - 1, "all_alone": 1}[heavy]
+    print("batch of", len(Qs), "queries, heavy split", heavy, flush=True)
+    got = gsm.match_batch(G, Qs, root=BATCH_SLICE, batch_heavy_pairs=hp)
+    bad = np.nonzero(got != expect)[0]
+    assert bad.size == 0, [(int(k), int(got[k]), int(expect[k])) for k in bad[:10]]
+
+
+def test_batch_slices_small_budget(batch_workload):
+    # the same counts when the shared frontiers are cut into many chunks
+    w, G, Qs, expect = batch_workload
+    sub = list(range(0, len(Qs), 7))
+    got = gsm.match_batch(G, [Qs[k] for k in sub], root=BATCH_SLICE, budget=96 << 20,
+                          batch_heavy_pairs=(1 << 64) - 1)
+    np.testing.assert_array_equal(got, expect[sub])
+
+
+def test_served_arrivals_on_slices_equal_oracle():
+    w = W.serving(nq=SERVING_ARRIVALS)
+    fp, rows = golden("serving_slice_counts.txt")
+    assert fingerprint(w.graph, w.queries) == fp
+    G = gsm.Graph.from_workload(w.graph)
+    pool = {}
+    Qs = []
+    for qr in w.queries:
+        if id(qr) not in pool:
+            pool[id(qr)] = gsm.Query.from_workload(qr)
+        Qs.append(pool[id(qr)])
+    srv = gsm.Server(G, workers=4, arena_bytes=8 << 30, max_batch=32)
+    try:
+        tickets = [srv.submit(Q, root=(0, SERVING_MOD, k % SERVING_MOD)) for k, Q in enumerate(Qs)]
+        res = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    got = np.array([r["count"] for r in res], dtype=np.uint64)
+    expect = np.array([int(r[2]) for r in rows], dtype=np.uint64)
+    bad = np.nonzero(got != expect)[0]
+    assert bad.size == 0, [(int(k), int(got[k]), int(expect[k])) for k in bad[:10]]
+    assert max(r["batch_size"] for r in res) > 1  # arrivals were batched together
+
+
+def test_large_graph_slices_equal_oracle():
+    g = W.large_graph()
+    fp, rows = golden("large_slice_counts.txt")
+    shapes = []
+    for r in rows:
+        if r[0] not in shapes:
+            shapes.append(r[0])
+    assert fingerprint(g, [W.shape(s) for s in shapes]) == fp
+    G = gsm.Graph.from_workload(g)
+    nonzero = 0
+    for name, rem, cnt in rows:
+        Q = gsm.Query.from_workload(W.shape(name))
+        print("large", name, "residue", rem, flush=True)
+        c, _, _ = gsm.match(G, Q, root=(0, LARGE_MOD, int(rem)))
+        assert c == int(cnt), (name, rem, c, cnt)
+        nonzero += c > 0
+    assert nonzero >= len(rows) // 2
