@@ -269,6 +269,35 @@ gsm_status gsm_match(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, 
                      int32_t *rows, uint64_t rows_cap, uint64_t *rows_written);
 
 /*
+ * gsm_match for callers that cannot allocate device memory: code that must
+ * not call hipMalloc (tight serving loops, harnesses that forbid it, work
+ * recorded around HIP graph capture).  Same arguments, results and errors as
+ * gsm_match; no device memory is allocated or freed by the call, nor by any
+ * library routine it calls.
+ * Every buffer of the call (candidate masks, level frontiers, scans, output
+ * staging, counters) lives in one device array of
+ * GSM_NOALLOC_SCRATCH_BYTES bytes that the library holds on each device it
+ * runs on until the process ends.  Limits:
+ *   - the graph's candidate masks and first frontier must fit:
+ *     29 n + 4 KiB bytes plus 28 KiB of fixed overhead, so n up to about
+ *     2.2 million vertices; a larger graph returns GSM_E_BUDGET with the sizes
+ *     in gsm_last_error();
+ *   - opts->memory_budget_bytes is capped at what the array holds (frontier
+ *     chunks are smaller than with gsm_match, so large outputs take more
+ *     launches; results are identical);
+ *   - GSM_MATCH_SORT_ROWS returns GSM_E_UNSUPPORTED (sort with gsm_sort_rows,
+ *     which allocates), opts->profile is ignored.
+ * Calls on one device share its array and are serialised inside the library
+ * (a call waits for the previous one); the array keeps the last call's
+ * contents, and every call clears its counters before use.  Two processes
+ * each have their own array.  Rows handed to an emit callback point into the
+ * array and are valid only during the callback.
+ */
+#define GSM_NOALLOC_SCRATCH_BYTES (64ull << 20)
+gsm_status gsm_match_noalloc(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts, uint64_t *count,
+                             int32_t *rows, uint64_t rows_cap, uint64_t *rows_written);
+
+/*
  * Sorts nrows rows of q int32 ids (row-major) into ascending lexicographic
  * order in place, on the device, on the graph's stream-ordered workspace
  * (the embedding list of Alg. 1 output M, as a sorted set).

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgsm.so")
-SOURCES = ["kernels.hip", "sort.hip", "batch_aux.hip", "plan.cpp", "capi.cpp", "match.cpp", "batch.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "sort.hip", "batch_aux.hip", "plan.cpp", "capi.cpp", "match.cpp", "batch.cpp", "server.cpp", "noalloc.hip"]
 ARCH = os.environ.get("GSM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -117,6 +117,8 @@ def _load():
     lib.gsm_filter.argtypes = [vp, vp, P(MatchOpts), vp]
     lib.gsm_match.restype = ctypes.c_int
     lib.gsm_match.argtypes = [vp, vp, P(MatchOpts), P(u64), vp, u64, P(u64)]
+    lib.gsm_match_noalloc.restype = ctypes.c_int
+    lib.gsm_match_noalloc.argtypes = [vp, vp, P(MatchOpts), P(u64), vp, u64, P(u64)]
     lib.gsm_match_min_budget.restype = ctypes.c_int
     lib.gsm_match_min_budget.argtypes = [vp, vp, i32, P(u64)]
     lib.gsm_sort_rows.argtypes = [vp, vp, u64, i32, i32, vp]
@@ -272,6 +274,9 @@ def filter(graph: Graph, query: Query, **kw) -> np.ndarray:
     return out
 
 
+NOALLOC_SCRATCH_BYTES = 64 << 20  # GSM_NOALLOC_SCRATCH_BYTES
+
+
 def match(graph: Graph, query: Query, rows=None, rows_cap: Optional[int] = None, emit=None,
           emit_device=None, **kw):
     """Count (and list) embeddings.
@@ -283,6 +288,12 @@ def match(graph: Graph, query: Query, rows=None, rows_cap: Optional[int] = None,
     value stops the match.  Returns (count, rows_or_None, stats dict).
     """
     return _match("gsm_match", graph, query, rows, rows_cap, emit, emit_device, **kw)
+
+
+def match_noalloc(graph: Graph, query: Query, rows=None, rows_cap: Optional[int] = None, emit=None,
+                  emit_device=None, **kw):
+    """match() through gsm_match_noalloc: no device allocation inside the call."""
+    return _match("gsm_match_noalloc", graph, query, rows, rows_cap, emit, emit_device, **kw)
 
 
 def _match(entry: str, graph: Graph, query: Query, rows, rows_cap, emit, emit_device, **kw):
