@@ -1,17 +1,21 @@
 #!/usr/bin/env python3
 """Throughput of the HIP subgraph matcher on one MI355X.
 
-Workload (default): R-MAT data graph, 2^17 vertices, edge factor 8,
-(a, b, c) = (0.57, 0.19, 0.19), 16 Zipf(1.0) labels; 20 induced random-walk
-queries with 5-6 vertices and 5-9 edges.  One step enumerates every embedding
-of all 20 queries: filter, level-by-level expansion in memory-bounded chunks,
-and every embedding row materialised in device memory (a bounded output chunk
-handed to a device-side consumer, which discards it).
+Workload (default, ``--workload large``): R-MAT data graph, 2^21 vertices,
+edge factor 16, (a, b, c) = (0.57, 0.19, 0.19), unlabelled.  One step lists
+every triangle embedding into HBM (5.7 x 10^9 rows, handed chunk by chunk to
+a device-side consumer), counts the triangles once per subgraph, and counts
+the 4-clique, 5-cycle and house+tail embeddings on fixed root slices.
 
-Prints one JSON line: embeddings/s over the timed steps, the dominant kernel's
-roofline (algorithmic bytes of the expansion launches over their HIP-event
-time), and the CPU oracle timed on a bounded sample of the same workload.
-Progress goes to stderr.
+``--workload powerlaw`` enumerates the 20 power-law queries (R-MAT 2^17, 16
+Zipf labels); ``batch`` compares batched and per-launch queries/s; ``serving``
+reports p50/p99 latency under Poisson arrivals.
+
+Prints one JSON line: embeddings/s over the timed steps, the expansion
+kernel's roofline (algorithmic bytes over its HIP-event time, and the HBM
+bytes rocprofv3 measured for the same command when a record of them matches
+the current sources), and the CPU oracle timed on a bounded sample of the
+same workload.  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -32,18 +36,81 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
-    """HBM bytes per expansion launch from the committed rocprofv3 counter
-    record, or None when the kernels changed since it was taken."""
+# Sources whose change invalidates a stored traffic record: the kernels and
+# every host file that chooses launch shapes, chunks or what is launched.
+TRAFFIC_SOURCES = ["paper_2003_01527_amd/csrc/" + f for f in
+                   ("kernels.hip", "match.cpp", "batch.cpp", "plan.cpp", "capi.cpp", "gsm_internal.h")] + ["bench.py"]
+
+
+def sources_sha1():
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", "k_expand_powerlaw_traffic.json")
-    src = os.path.join(ROOT, "paper_2003_01527_amd", "csrc", "kernels.hip")
+    h = hashlib.sha1()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_record_path(workload):
+    return os.path.join(ROOT, "profiles", "k_expand_%s_traffic.json" % workload)
+
+
+def measured_traffic(workload):
+    """HBM bytes per expansion launch from the committed rocprofv3 counter
+    record of this workload, or None when any source it depends on changed
+    since it was taken."""
     try:
-        rec = json.load(open(rec_path))
-        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
-    except OSError:
+        rec = json.load(open(traffic_record_path(workload)))
+        sha = sources_sha1()
+    except (OSError, ValueError):
         return None
-    return rec["traffic_bytes_per_launch"] if rec.get("kernels_hip_sha1") == sha else None
+    return rec["traffic_bytes_per_launch"] if rec.get("sources_sha1") == sha else None
+
+
+def write_traffic_record(workload, fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes):
+    """Builds the traffic record from four rocprofv3 --pmc runs (csv output):
+    FETCH_SIZE and WRITE_SIZE of the bench command (k_expand dispatches), and
+    of a plain device copy of copy_bytes bytes (the calibration: what each
+    counter reads per byte actually moved)."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter, match):
+        tot, n = 0.0, 0
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r.get("Counter_Name") == counter and match in r.get("Kernel_Name", ""):
+                    tot += float(r["Counter_Value"])
+                    n += 1
+        return tot, n
+
+    f_kib, nf = per_kernel(fetch_dir, "FETCH_SIZE", "k_expand")
+    w_kib, nw = per_kernel(write_dir, "WRITE_SIZE", "k_expand")
+    cf_kib, _ = per_kernel(cfetch_dir, "FETCH_SIZE", "copyBuffer")
+    cw_kib, _ = per_kernel(cwrite_dir, "WRITE_SIZE", "copyBuffer")
+    fscale = copy_bytes / (cf_kib * 1024.0)
+    wscale = copy_bytes / (cw_kib * 1024.0)
+    fetch = f_kib * 1024.0 * fscale
+    write = w_kib * 1024.0 * wscale
+    launches = max(nf, 1)
+    rec = {"kernel": "k_expand", "workload": workload, "sources_sha1": sources_sha1(),
+           "launches": launches, "fetch_bytes": round(fetch), "write_bytes": round(write),
+           "traffic_bytes_per_launch": round((fetch + write) / launches),
+           "fetch_scale": fscale, "write_scale": wscale, "dispatch_records": [nf, nw]}
+    with open(traffic_record_path(workload), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec), flush=True)
+
+
+def host_cores():
+    """Threads the CPU baseline uses (the host CPUs this process may run on,
+    at most 16, the CPU share of one GPU on the measurement boxes) and the
+    host's own count."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return min(16, avail), os.cpu_count() or 1
 
 
 def main():
@@ -59,8 +126,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--items", type=int, default=0)
-    ap.add_argument("--workload", choices=["powerlaw", "batch", "serving", "large"], default="powerlaw",
-                    help="powerlaw: embeddings/s (default); batch: batched vs per-launch queries/s; "
+    ap.add_argument("--workload", choices=["large", "powerlaw", "batch", "serving"], default="large",
+                    help="large: embeddings/s on the 2^21-vertex graph (default); powerlaw: embeddings/s "
+                         "on the 20 labelled queries; batch: batched vs per-launch queries/s; "
                          "serving: p50/p99 latency and queries/s under Poisson arrivals")
     ap.add_argument("--arrivals", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--workers", type=int, default=4, help="serving: worker streams")
@@ -70,7 +138,13 @@ def main():
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (calibrates "
                          "the HBM byte counters of rocprofv3) and exit")
+    ap.add_argument("--write-traffic-record", nargs=4, metavar=("FETCH", "WRITE", "CFETCH", "CWRITE"),
+                    help="rocprofv3 --pmc output folders of FETCH_SIZE and WRITE_SIZE for this workload "
+                         "and for a --copy-gib 1 run: store the traffic record and exit")
     args = ap.parse_args()
+
+    if args.write_traffic_record:
+        return write_traffic_record(args.workload, *args.write_traffic_record, copy_bytes=1 << 30)
 
     if args.copy_gib > 0:
         import torch
@@ -89,18 +163,20 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-
-    from paper_2003_01527_amd import gsm
-    from paper_2003_01527_amd import workloads as W
-
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "serving":
         return bench_serving(args)
     if args.workload == "large":
         return bench_large(args)
+    return bench_powerlaw(args)
+
+
+def bench_powerlaw(args):
+    import torch
+
+    from paper_2003_01527_amd import gsm
+    from paper_2003_01527_amd import workloads as W
 
     t = time.time()
     w = W.powerlaw()
@@ -153,7 +229,7 @@ def main():
 
     value = tot_emb / elapsed
     achieved = (tot_bytes / 1e9) / (tot_ms / 1e3) if tot_ms > 0 else 0.0
-    traffic = measured_traffic() if args.mode == "enumerate" and not (args.wg or args.items) else None
+    traffic = measured_traffic("powerlaw") if args.mode == "enumerate" and not (args.wg or args.items) else None
     roofline = {
         "kernel": "k_expand (expand-verify-compact)",
         "bound": "hbm",
@@ -172,7 +248,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        cores = min(16, os.cpu_count() or 1)
+        cores, nproc = host_cores()
         mod = args.cpu_slice
         t = time.perf_counter()
         emb = 0
@@ -181,6 +257,7 @@ def main():
             emb += c
         dt = time.perf_counter() - t
         cpu = {"value": round(emb / dt, 1), "unit": "embeddings/s", "cores": cores, "kind": "oracle",
+               "host_nproc": nproc,
                "sample": "all %d queries restricted to the root slice splitmix64(f(query vertex 0)) %% %d == 0 "
                          "(%d embeddings, %.1f s, count only)" % (len(queries), mod, emb, dt)}
         log("cpu baseline: %s" % cpu)
@@ -220,7 +297,7 @@ def main():
 # and house+tail counted on deterministic root slices (their full counts take
 # minutes to hours even on the GPU).  (label, shape, root slice, list, unique)
 LARGE_STEP = [("K3", "K3", None, True, False), ("K3 unique", "K3", None, False, True),
-              ("K4", "K4", (0, 256, 1), False, False), ("C5", "C5", (0, 1 << 16, 1), False, False),
+              ("K4", "K4", (0, 512, 1), False, False), ("C5", "C5", (0, 1 << 17, 1), False, False),
               ("house_tail", "house_tail", (0, 1 << 20, 1), False, False)]
 
 
@@ -289,15 +366,18 @@ def bench_large(args):
         e["listed"] = emit
         e["unique"] = uniq
     achieved = (tot_bytes / 1e9) / (tot_ms / 1e3) if tot_ms > 0 else 0.0
+    launches = max(tot_launch, 1)
+    traffic = measured_traffic("large") if not (args.wg or args.items) else None
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        cores = min(16, os.cpu_count() or 1)
+        cores, nproc = host_cores()
         t = time.perf_counter()
         c, _ = oracle.match(g, W.shape("K3"), rows=False, threads=cores, root=(0, 64, 0))
         dt = time.perf_counter() - t
         cpu = {"value": round(c / dt, 1), "unit": "embeddings/s", "cores": cores, "kind": "oracle",
+               "host_nproc": nproc,
                "sample": "triangle embeddings with splitmix64(f(vertex 0)) %% 64 == 0 (%d, %.1f s, count only)"
                          % (c, dt)}
         log("cpu baseline: %s" % cpu)
@@ -315,9 +395,10 @@ def bench_large(args):
         "dtype": "int32",
         "data": "synthetic",
         "config": {
-            "workload": "large unlabelled R-MAT 2^21 ef16 (0.57,0.19,0.19): triangle embeddings listed "
-                        "into HBM, triangles counted once per subgraph; 4-clique, 5-cycle, house+tail "
-                        "counted on root slices",
+            "workload": "large unlabelled R-MAT 2^21 ef16 (0.57,0.19,0.19): every triangle embedding listed "
+                        "into HBM, triangles counted once per subgraph (not in value), 4-clique on the root slice "
+                        "splitmix64(f(0)) %% 512 == 1, 5-cycle on %% 2^17 == 1, house+tail on %% 2^20 == 1, "
+                        "counted",
             "graph_vertices": g.n,
             "graph_csr_entries": g.nnz,
             "per_query": per,
@@ -330,9 +411,14 @@ def bench_large(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per k_expand launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_frac": (round(traffic * launches / (tot_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                             if traffic and tot_ms > 0 else None),
+            "alg_bytes_per_launch": tot_bytes // launches,
             "alg_bytes_per_step": tot_bytes // max(args.steps, 1),
             "kernel_ms_per_step": round(tot_ms / max(args.steps, 1), 3),
+            "avg_launch_us": round(1e3 * tot_ms / launches, 1),
             "launches_per_step": tot_launch // max(args.steps, 1),
         },
         "cpu_baseline": cpu,

@@ -63,47 +63,14 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *sw, ui
   return before + inc - v;
 }
 
-// Index of w in the ascending list c[0..n), or -1.
-// Lists longer than kInterpMin are searched by interpolation first
-// (Peterson 1957; Perl, Itai and Avni 1978): the next probe goes where w
-// falls between the values at the window's ends.  Neighbour ids of a vertex
-// are spread close to uniformly over the id range when ids are randomly
-// permuted (as in R-MAT graphs); on such a list of 10^5 ids five steps and a
-// short halving take about 5 loads where halving alone takes 18.  Whatever
-// the distribution, at most kInterpSteps interpolation probes are taken
-// before halving what is left, so the cost stays O(log n); every probe lies
-// inside the window, so the result is the same as a plain binary search's.
-constexpr uint32_t kInterpMin = 8;
-constexpr int kInterpSteps = 5;
-
+// Index of w in the ascending list c[0..n), or -1: the window is halved down
+// to its last entry <= w, with 32-bit offsets from the list start, then one
+// compare.  (Interpolation probes were measured slower on the 2^21-vertex
+// R-MAT graph: lanes of a wave search nearby keys, so halving's first probes
+// are shared loads, while every interpolation probe is a separate one.)
 __device__ __forceinline__ int32_t find_sorted(const int32_t *c, uint32_t n, int32_t w) {
   if (n == 0) return -1;
-  uint32_t b = 0, m = n;  // halving window c[b .. b+m)
-  if (n > kInterpMin) {
-    uint32_t lo = 0, hi = n - 1;
-    int32_t vlo = c[0], vhi = c[hi];
-    if (w <= vlo) return w == vlo ? 0 : -1;
-    if (w >= vhi) return w == vhi ? (int32_t)hi : -1;
-    // vlo < w < vhi: w can only sit strictly between lo and hi
-    for (int k = 0; k < kInterpSteps && hi - lo > kInterpMin; ++k) {
-      const float f = (float)(w - vlo) * __builtin_amdgcn_rcpf((float)(vhi - vlo));
-      uint32_t p = lo + 1 + (uint32_t)(f * (float)(hi - lo - 1));
-      p = min(p, hi - 1);
-      const int32_t v = c[p];
-      if (v == w) return (int32_t)p;
-      if (v < w) {
-        lo = p;
-        vlo = v;
-      } else {
-        hi = p;
-        vhi = v;
-      }
-    }
-    b = lo + 1;
-    m = hi - lo - 1;
-    if (m == 0) return -1;
-  }
-  // halve the window down to its last entry <= w, then one compare
+  uint32_t b = 0, m = n;
   while (m > 1) {
     const uint32_t h = m >> 1;
     b = (c[b + h] <= w) ? b + h : b;

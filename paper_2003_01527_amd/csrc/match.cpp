@@ -460,17 +460,21 @@ struct Matcher {
     return ws.h_counters[kCntResult];
   }
 
-  // Algorithmic bytes of the expansion launches (what the method must move):
-  // per input row its ids, anchor position, range start and scan entry; per
-  // pair a neighbour id and a candidate-mask entry; per binary-search step one
-  // neighbour id (4 bytes); per written row its ids, range size, range start
-  // and anchor position plus two range offsets read to choose the anchor;
-  // per emitted embedding its q ids.
+  // Algorithmic bytes of the expansion launches (what the method must move),
+  // per row r of level i: its i ids and its anchor's two CSR offsets
+  // (4i + 8); per (row, neighbour) pair the neighbour id and its candidate
+  // mask entry (4 + 2; pairs are the anchor's neighbours of the new vertex's
+  // label); per back-edge other than the anchor the list's two offsets (8)
+  // and 4 bytes per step of a binary search of that list, for every pair that
+  // reaches the check; per row written to the next level its i+1 ids; per
+  // embedding handed out its q ids.  Bookkeeping this implementation adds
+  // (range starts, scan entries, anchor positions) is not counted.
   void finish_stats(uint64_t count) {
     uint64_t b = 0;
     for (int i = 1; i < p.q; ++i) {
-      b += st.rows[i - 1] * (4ull * i + 1 + 8 + 8) + st.pairs[i] * (4 + 2);
-      if (i + 1 < p.q) b += st.rows[i] * (4ull * (i + 1) + 4 + 8 + 1 + 16);
+      const uint64_t others = (uint64_t)std::max(0, __builtin_popcount(p.backmask[i]) - 1);
+      b += st.rows[i - 1] * (4ull * i + 8 + 8 * others) + st.pairs[i] * (4 + 2);
+      if (i + 1 < p.q) b += st.rows[i] * 4ull * (i + 1);
     }
     b += st.probes * 4;
     if (rows_user || o.emit) b += count * 4ull * p.q;
