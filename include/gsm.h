@@ -182,6 +182,7 @@ typedef struct gsm_stats {
   uint64_t expand_launches;             /* expansion kernel launches */
   double ms_expand;                     /* summed expansion kernel time (HIP events; needs profile) */
   double ms_total;                      /* host wall time of the call */
+  uint64_t frontier_bytes;              /* bytes of intermediate rows written (packed or not) */
 } gsm_stats;
 
 /* Emit callback: receives nrows rows, valid only during the call: host memory,
@@ -240,6 +241,15 @@ typedef struct gsm_match_opts {
  * costs one more membership search per surviving pair.  Combines with the
  * other flags; single-query matching only. */
 #define GSM_MATCH_INDUCED 16u
+/* Packed frontier (the paper's compact storage of partial results, Sec. 3.2
+ * and 3.3, read as a reversible encoding): rows of the intermediate levels
+ * are stored as b-bit ids laid end to end in 32-bit words, b = bit width of
+ * n - 1, at every level where that takes fewer words than ids (e.g. 4 ids of
+ * a 2^21-vertex graph in 12 bytes instead of 16) and the level's rows can be
+ * staged whole in LDS.  Rows are decoded exactly, so the
+ * result is unchanged; more rows fit a memory budget.  Single-query matching
+ * only. */
+#define GSM_MATCH_PACK_FRONTIER 32u
 
 /* Fills defaults (struct_size set, budget 0, rounds 1, degree and NE on, no slice). */
 void gsm_match_opts_init(gsm_match_opts *o);

@@ -381,8 +381,10 @@ extern "C" gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query
     gsm_match_opts_init(&d);
     const gsm_match_opts &o = opts ? *opts : d;
     if (o.struct_size >= offsetof(gsm_match_opts, flags) + sizeof(uint32_t) &&
-        (o.flags & (GSM_MATCH_UNIQUE | GSM_MATCH_LOOKAHEAD | GSM_MATCH_SORT_ROWS | GSM_MATCH_INDUCED))) {
-      gsm::set_error("gsm_match_batch: unique, induced, look-ahead and sorted modes are single-query options");
+        (o.flags & (GSM_MATCH_UNIQUE | GSM_MATCH_LOOKAHEAD | GSM_MATCH_SORT_ROWS | GSM_MATCH_INDUCED |
+                    GSM_MATCH_PACK_FRONTIER))) {
+      gsm::set_error("gsm_match_batch: unique, induced, look-ahead, sorted and packed modes are single-query "
+                     "options");
       return GSM_E_UNSUPPORTED;
     }
     if (o.rows_on_device || o.emit) {

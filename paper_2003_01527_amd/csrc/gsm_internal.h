@@ -283,6 +283,10 @@ struct ExpandArgs {
   uint16_t *qid_out;
   const BatchLevel *blev;  // [nq * kMaxQ], entry (k, i)
   uint64_t *counts;        // per-query embedding counts
+  // packed frontier rows (b = pack_bits bits per id, ceil(i*b/32) 32-bit
+  // words per row of i ids): the input rows (pack_in, then they are always
+  // staged in LDS) and the next level's rows (pack_out, kModeNext)
+  int32_t pack_bits, pack_in, pack_out;
   int32_t staged;        // output rows pass through LDS (dynamic shared memory)
   int32_t stage_in;      // the tile's input rows are copied to LDS
   int32_t stage_out_ok;  // the caller allows output staging
@@ -290,6 +294,8 @@ struct ExpandArgs {
 };
 
 void launch_expand(const ExpandArgs &a, int mode, int wg, int items, hipStream_t s);
+// Most LDS a launch uses to stage its tile's input and output rows.
+constexpr size_t kExpandStageBytes = 48 * 1024;
 
 // Batched helpers: qpairs[q] += W[r] over the *n_dev rows r of query qid[r];
 // rows whose query is marked in evicted get W = 1 and qid = retired (a query

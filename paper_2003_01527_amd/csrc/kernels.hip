@@ -227,6 +227,16 @@ __global__ __launch_bounds__(256) void k_refine_heavy(DeviceGraph g, QueryArgs q
 
 // ------------------------------------------------------ first frontier --
 
+// Column j of a packed frontier row (b-bit ids laid end to end from bit 0 of
+// the row's first 32-bit word; b <= 31, so an id spans at most two words):
+// the reversible packing of partial results.
+__device__ __forceinline__ int32_t unpack_id(const uint32_t *row, uint32_t j, uint32_t b) {
+  const uint32_t bit = j * b, wd = bit >> 5, sh = bit & 31;
+  uint32_t v = row[wd] >> sh;
+  if (sh + b > 32) v |= row[wd + 1] << (32 - sh);
+  return (int32_t)(v & ((1u << b) - 1u));
+}
+
 // Neighbour range of x that holds label l: [base, base + size) in g.gather.
 __device__ __forceinline__ uint32_t label_range(const DeviceGraph &g, int32_t x, int32_t l,
                                                 int64_t &base) {
@@ -541,7 +551,12 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
       if (sS[k] < len && sS[k + 1] >= len) s_R = (uint32_t)k + 1;  // exactly one k
     __syncthreads();
     const uint32_t R = s_R, lead = s_lead;
-    if (stage_in) {
+    if (stage_in && a.pack_in) {
+      // packed rows: ceil(i*b/32) words each, column j in bits [j*b, j*b+b)
+      const uint32_t b = (uint32_t)a.pack_bits, nw = (uint32_t)((i * b + 31) / 32);
+      const uint32_t *src = reinterpret_cast<const uint32_t *>(a.rows_in) + r0 * (uint64_t)nw;
+      for (uint32_t e = tid; e < R * (uint32_t)i; e += WG) s_in[e] = unpack_id(src + (e / i) * nw, e % i, b);
+    } else if (stage_in) {
       const int32_t *src = a.rows_in + r0 * (uint64_t)i;
       for (uint32_t e = tid; e < R * (uint32_t)i; e += WG) s_in[e] = src[e];
     }
@@ -844,6 +859,24 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
               a.apos_out[pos] = napos[it];
               if (MODE == kModeBatch) a.qid_out[pos] = (uint16_t)qk[it];
             }
+            if (MODE == kModeNext && a.pack_out) {
+              // packed next-level row: word d holds the bits [32d, 32d+32) of
+              // the columns laid end to end at b bits each
+              const uint32_t b = (uint32_t)a.pack_bits, nw = (uint32_t)((width * b + 31) / 32);
+              uint32_t *o32 = reinterpret_cast<uint32_t *>(a.rows_out) + pos * (uint64_t)nw;
+              for (uint32_t d = 0; d < nw; ++d) {
+                uint32_t word = 0;
+                for (int c = 0; c < width; ++c) {
+                  const int32_t lo = c * (int32_t)b - 32 * (int32_t)d;  // column start relative to the word
+                  if (lo >= 32 || lo + (int32_t)b <= 0) continue;
+                  const uint32_t v =
+                      (uint32_t)(c == i ? w : (stage_in ? s_in[k * i + c] : a.rows_in[(r0 + k) * i + c]));
+                  word |= lo >= 0 ? v << lo : v >> -lo;
+                }
+                o32[d] = word;
+              }
+              continue;
+            }
             int32_t *o;
             if (a.staged) {
               o = s_out + loc * (uint32_t)width;
@@ -935,7 +968,7 @@ __global__ void k_zero_u64(uint64_t *p, size_t count) {
     p[k] = 0;
 }
 
-constexpr size_t kMaxStageBytes = 48 * 1024;
+constexpr size_t kMaxStageBytes = kExpandStageBytes;
 
 template <int WG, int ITEMS>
 void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
@@ -952,8 +985,11 @@ void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
   const size_t in_bytes = TILE * (size_t)a.L.i * sizeof(int32_t);
   const size_t out_bytes = TILE * (size_t)width * sizeof(int32_t);
   a.stage_in = (in_bytes <= kMaxStageBytes) ? 1 : 0;
-  a.staged = (a.stage_out_ok && mode != kModeCount && mode != kModeBatchLast &&
-              (a.stage_in ? in_bytes : 0) + out_bytes <= kMaxStageBytes)
+  if (a.pack_in && !a.stage_in) throw Error{GSM_E_DEVICE, "packed frontier rows need staging"};
+  if ((a.pack_in || a.pack_out) && (mode == kModeBatch || mode == kModeBatchLast))
+    throw Error{GSM_E_DEVICE, "packed frontier rows in a batched launch"};
+  a.staged = (a.stage_out_ok && !(mode == kModeNext && a.pack_out) && mode != kModeCount &&
+              mode != kModeBatchLast && (a.stage_in ? in_bytes : 0) + out_bytes <= kMaxStageBytes)
                  ? 1
                  : 0;
   const size_t smem = (a.stage_in ? in_bytes : 0) + (a.staged ? out_bytes : 0);

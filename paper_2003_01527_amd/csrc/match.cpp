@@ -36,6 +36,7 @@ struct Options {
   bool lookahead = false;
   bool unique = false;
   bool induced = false;
+  bool pack = false;
 };
 
 Options read_opts(const gsm_match_opts *o, int q) {
@@ -63,6 +64,7 @@ Options read_opts(const gsm_match_opts *o, int q) {
     r.lookahead = (o->flags & GSM_MATCH_LOOKAHEAD) != 0;
     r.unique = (o->flags & GSM_MATCH_UNIQUE) != 0;
     r.induced = (o->flags & GSM_MATCH_INDUCED) != 0;
+    r.pack = (o->flags & GSM_MATCH_PACK_FRONTIER) != 0;
   }
   if (r.rounds < 0 || r.rounds > 64) throw Error{GSM_E_INVALID_ARG, "filter_rounds out of [0, 64]"};
   if (r.root_q >= q) throw Error{GSM_E_INVALID_ARG, "root_qvertex >= q"};
@@ -101,6 +103,8 @@ struct Matcher {
   DeviceGraph dg;
   uint64_t cap[kMaxQ];  // max rows per level buffer
   uint64_t *dcnt;       // device counters
+  int pack_bits = 0;          // bits per packed id (bit width of n - 1)
+  bool packed[kMaxQ] = {};    // rows of level i are packed
   // output
   int32_t *rows_user = nullptr;
   uint64_t rows_cap = 0;
@@ -122,6 +126,19 @@ struct Matcher {
     std::memset(&st, 0, sizeof(st));
     st.struct_size = sizeof(st);
     st.q = p.q;
+    if (o.pack) {
+      pack_bits = 1;
+      while (pack_bits < 31 && (int64_t(1) << pack_bits) < g.n) ++pack_bits;
+      // level i is packed when that saves bytes and its consumer can stage
+      // its rows in LDS (the decoder runs there)
+      for (int i = 2; i < p.q; ++i)
+        packed[i] = (i * pack_bits + 31) / 32 < i && (uint64_t)o.wg * o.items * i * 4 <= kExpandStageBytes;
+    }
+  }
+
+  // bytes of one row of level i in its buffer
+  uint64_t row_bytes(int i) const {
+    return 4 * (uint64_t)(packed[i] ? (i * pack_bits + 31) / 32 : i);
   }
 
   // A call that fails part-way may have launches in flight on the stream;
@@ -212,7 +229,7 @@ struct Matcher {
     for (int i = 0; i < kMaxQ; ++i) cap[i] = 0;
     cap[1] = n;
     for (int i = 2; i < p.q; ++i) {
-      cap[i] = rest / shares / (uint64_t)(4 * i + 21);
+      cap[i] = rest / shares / (row_bytes(i) + 21);
       if (cap[i] < 1) throw Error{GSM_E_BUDGET, "memory budget below one row of level " + std::to_string(i)};
     }
     if (emit_host) {
@@ -264,7 +281,7 @@ struct Matcher {
     take(ws.cmask2, n * 2);
     for (int i = 1; i < p.q; ++i) {
       const uint64_t c = cap[i];
-      take(ws.rows[i], c * 4 * (uint64_t)i);
+      take(ws.rows[i], c * row_bytes(i));
       take(ws.W[i], c * 4);
       take(ws.apos[i], c);
       take(ws.abase[i], c * 8);
@@ -274,7 +291,7 @@ struct Matcher {
   }
 
   void reserve_level(int i, uint64_t rows) {
-    ws.rows[i].reserve(rows * 4 * (uint64_t)i, s);
+    ws.rows[i].reserve(rows * row_bytes(i), s);
     ws.W[i].reserve(rows * 4, s);
     ws.apos[i].reserve(rows, s);
     ws.abase[i].reserve(rows * 8, s);
@@ -370,6 +387,9 @@ struct Matcher {
     a.S = ws.S[i].as<uint64_t>();
     a.n_rows = N;
     a.L = level_args(i);
+    a.pack_bits = pack_bits;
+    a.pack_in = packed[i] ? 1 : 0;
+    a.pack_out = (i + 1 < p.q && packed[i + 1]) ? 1 : 0;
     if (!last) {
       const uint64_t c = cap[i + 1];
       for (uint64_t b = 0; b < P && !cancelled; b += c) {
@@ -479,6 +499,7 @@ struct Matcher {
     b += st.probes * 4;
     if (rows_user || o.emit) b += count * 4ull * p.q;
     st.alg_bytes = b;
+    for (int i = 2; i < p.q; ++i) st.frontier_bytes += st.rows[i - 1] * row_bytes(i);
     if (o.profile) {
       double ms = 0;
       for (auto &pr : ev_pairs) {

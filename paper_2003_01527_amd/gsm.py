@@ -45,7 +45,8 @@ class Stats(ctypes.Structure):
                 ("pairs", ctypes.c_uint64 * MAXQ), ("chunks", ctypes.c_uint64 * MAXQ),
                 ("probes", ctypes.c_uint64), ("alg_bytes", ctypes.c_uint64),
                 ("filter_bytes", ctypes.c_uint64), ("expand_launches", ctypes.c_uint64),
-                ("ms_expand", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_expand", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("frontier_bytes", ctypes.c_uint64)]
 
     def as_dict(self):
         q = self.q
@@ -54,7 +55,7 @@ class Stats(ctypes.Structure):
                 "chunks": list(self.chunks[:q]), "probes": self.probes,
                 "alg_bytes": self.alg_bytes, "filter_bytes": self.filter_bytes,
                 "expand_launches": self.expand_launches, "ms_expand": self.ms_expand,
-                "ms_total": self.ms_total}
+                "ms_total": self.ms_total, "frontier_bytes": self.frontier_bytes}
 
 
 EMIT_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
@@ -231,12 +232,14 @@ FLAG_SORT_ROWS = 2
 FLAG_LOOKAHEAD = 4
 FLAG_UNIQUE = 8
 FLAG_INDUCED = 16
+FLAG_PACK_FRONTIER = 32
 
 
 def make_opts(budget: int = 0, filter_rounds: int = 1, use_degree: bool = True, use_ne: bool = True,
               stream=None, root=None, tile_items: int = 0, wg_size: int = 0, profile: bool = False,
               stats: Optional[Stats] = None, stage_output: bool = True, sort_rows: bool = False,
-              lookahead: bool = False, unique: bool = False, induced: bool = False, batch_heavy_pairs: int = 0) -> MatchOpts:
+              lookahead: bool = False, unique: bool = False, induced: bool = False, batch_heavy_pairs: int = 0,
+              pack_frontier: bool = False) -> MatchOpts:
     o = MatchOpts()
     _load().gsm_match_opts_init(ctypes.byref(o))
     o.memory_budget_bytes = int(budget)
@@ -252,7 +255,7 @@ def make_opts(budget: int = 0, filter_rounds: int = 1, use_degree: bool = True, 
     o.profile = 1 if profile else 0
     o.flags = ((0 if stage_output else FLAG_NO_OUTPUT_STAGING) | (FLAG_SORT_ROWS if sort_rows else 0)
                | (FLAG_LOOKAHEAD if lookahead else 0) | (FLAG_UNIQUE if unique else 0)
-               | (FLAG_INDUCED if induced else 0))
+               | (FLAG_INDUCED if induced else 0) | (FLAG_PACK_FRONTIER if pack_frontier else 0))
     o.batch_heavy_pairs = int(batch_heavy_pairs)
     if stats is not None:
         stats.struct_size = ctypes.sizeof(Stats)

@@ -47,7 +47,7 @@ def test_status_strings():
 def test_struct_sizes_match_header():
     # gsm_match_opts: u32 + pad, u64, 4 x i32, ptr, i32, 2 x u32, 3 ptrs, 3 x i32 (+pad)
     assert ctypes.sizeof(gsm.MatchOpts) == 104
-    assert ctypes.sizeof(gsm.Stats) == 8 + 8 + 3 * 16 * 8 + 4 * 8 + 2 * 8
+    assert ctypes.sizeof(gsm.Stats) == 8 + 8 + 3 * 16 * 8 + 4 * 8 + 2 * 8 + 8
     o = gsm.make_opts()
     assert o.struct_size == ctypes.sizeof(gsm.MatchOpts)
     assert o.filter_rounds == 1 and o.use_degree == 1 and o.use_ne == 1 and o.root_qvertex == -1
@@ -100,6 +100,7 @@ def test_binding_flags_match_header():
     assert defs["GSM_MATCH_LOOKAHEAD"] == gsm.FLAG_LOOKAHEAD
     assert defs["GSM_MATCH_UNIQUE"] == gsm.FLAG_UNIQUE
     assert defs["GSM_MATCH_INDUCED"] == gsm.FLAG_INDUCED
+    assert defs["GSM_MATCH_PACK_FRONTIER"] == gsm.FLAG_PACK_FRONTIER
     assert defs["GSM_MAX_QUERY_VERTICES"] == 16
     flags = gsm.make_opts(sort_rows=True, lookahead=True, unique=True, induced=True, stage_output=False).flags
     assert flags == (gsm.FLAG_SORT_ROWS | gsm.FLAG_LOOKAHEAD | gsm.FLAG_UNIQUE | gsm.FLAG_INDUCED
