@@ -227,6 +227,13 @@ typedef struct gsm_match_opts {
  * data vertex's neighbours (too few of its label, or none that is a candidate
  * outside the row).  Pure pruning: the result is unchanged. */
 #define GSM_MATCH_LOOKAHEAD 4u
+/* Two-step look-ahead (Sec. 3.3, k-look-ahead, k = 2; implies
+ * GSM_MATCH_LOOKAHEAD): the neighbour found for a later query neighbour must
+ * itself have, for each label among that query vertex's own neighbours, at
+ * least as many neighbours of that label (the four labels with most such
+ * neighbours are tested; labelled graphs with the label table only).  Pure
+ * pruning: the result is unchanged. */
+#define GSM_MATCH_LOOKAHEAD2 64u
 /* Unique-subgraph mode: one embedding per subgraph of the data graph that
  * the query maps onto (the paper's way of producing each node combination
  * once by visiting equivalent query nodes in increasing id order, Sec. 3.3).

@@ -382,7 +382,7 @@ extern "C" gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query
     const gsm_match_opts &o = opts ? *opts : d;
     if (o.struct_size >= offsetof(gsm_match_opts, flags) + sizeof(uint32_t) &&
         (o.flags & (GSM_MATCH_UNIQUE | GSM_MATCH_LOOKAHEAD | GSM_MATCH_SORT_ROWS | GSM_MATCH_INDUCED |
-                    GSM_MATCH_PACK_FRONTIER))) {
+                    GSM_MATCH_PACK_FRONTIER | GSM_MATCH_LOOKAHEAD2))) {
       gsm::set_error("gsm_match_batch: unique, induced, look-ahead, sorted and packed modes are single-query "
                      "options");
       return GSM_E_UNSUPPORTED;

@@ -153,6 +153,10 @@ struct QueryArgs {
   uint64_t qne[kMaxQ];
 };
 
+// Labels per later query vertex that the two-step look-ahead tests (those
+// with the most neighbours of that label first).
+constexpr int kLa2Labels = 4;
+
 // One expansion level: rows hold positions 0..i-1; position i is matched.
 struct LevelArgs {
   int32_t i;               // matched positions per input row
@@ -185,6 +189,14 @@ struct LevelArgs {
   int32_t la_label[kMaxQ];
   uint32_t la_qbit[kMaxQ];
   uint32_t la_need[kMaxQ];
+  // two-step look-ahead (la2 != 0): the witness found for look-ahead entry f
+  // (a neighbour of the new vertex that could take that later query vertex)
+  // must itself have at least la2_need[f][t] neighbours of label
+  // la2_label[f][t], t < la2_n[f]: the later query vertex's own neighbours
+  int32_t la2;
+  uint8_t la2_n[kMaxQ];
+  int32_t la2_label[kMaxQ][kLa2Labels];
+  uint32_t la2_need[kMaxQ][kLa2Labels];
 };
 
 // Longest label group of the new vertex that the look-ahead scans.

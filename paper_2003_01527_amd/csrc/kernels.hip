@@ -255,13 +255,15 @@ __device__ __forceinline__ uint32_t label_range(const DeviceGraph &g, int32_t x,
   return g.deg[x];
 }
 
-// One-step look-ahead (Sec. 3.3, k-look-ahead with k = 1) on a new row: the
-// ids row[0..i) already matched and w placed at position i.  Every later
-// query neighbour of position i must find its own image among w's
-// neighbours of its label: there must be at least la_need of them (those of
-// the matched neighbours included), and, for a label group short enough to
-// scan, one that is a candidate of that query vertex and not in the row.
-// Failing either, no extension of the row can be an embedding.
+// k-look-ahead (Sec. 3.3) on a new row: the ids row[0..i) already matched
+// and w placed at position i.  One step: every later query neighbour of
+// position i must find its own image among w's neighbours of its label:
+// there must be at least la_need of them (those of the matched neighbours
+// included), and, for a label group short enough to scan, one that is a
+// candidate of that query vertex and not in the row.  Two steps (la2): that
+// neighbour must also have, for each label the later query vertex's own
+// neighbours carry, at least as many neighbours of that label.  Failing any,
+// no extension of the row can be an embedding.
 __device__ __forceinline__ bool lookahead_ok(const ExpandArgs &a, int32_t w, const int32_t *row) {
   for (int f = 0; f < a.L.la_n; ++f) {
     int64_t base;
@@ -274,7 +276,15 @@ __device__ __forceinline__ bool lookahead_ok(const ExpandArgs &a, int32_t w, con
       if (!((a.cmask[x] >> a.L.la_qbit[f]) & 1)) continue;
       bool used = false;
       for (int j = 0; j < a.L.i; ++j) used = used || row[j] == x;
-      found = !used;
+      if (used) continue;
+      // two steps: x would take the later query vertex, whose neighbours of
+      // each label must then map to distinct neighbours of x of that label
+      bool enough = true;
+      for (int e = 0; a.L.la2 && e < a.L.la2_n[f] && enough; ++e) {
+        int64_t xb;
+        enough = label_range(a.g, x, a.L.la2_label[f][e], xb) >= a.L.la2_need[f][e];
+      }
+      found = enough;
     }
     if (!found) return false;
   }

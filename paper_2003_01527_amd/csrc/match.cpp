@@ -34,6 +34,7 @@ struct Options {
   int stage_out = 1;
   bool sort = false;
   bool lookahead = false;
+  bool lookahead2 = false;
   bool unique = false;
   bool induced = false;
   bool pack = false;
@@ -61,7 +62,8 @@ Options read_opts(const gsm_match_opts *o, int q) {
   if (o->struct_size >= offsetof(gsm_match_opts, flags) + sizeof(uint32_t)) {
     r.stage_out = (o->flags & GSM_MATCH_NO_OUTPUT_STAGING) ? 0 : 1;
     r.sort = (o->flags & GSM_MATCH_SORT_ROWS) != 0;
-    r.lookahead = (o->flags & GSM_MATCH_LOOKAHEAD) != 0;
+    r.lookahead2 = (o->flags & GSM_MATCH_LOOKAHEAD2) != 0;
+    r.lookahead = r.lookahead2 || (o->flags & GSM_MATCH_LOOKAHEAD) != 0;
     r.unique = (o->flags & GSM_MATCH_UNIQUE) != 0;
     r.induced = (o->flags & GSM_MATCH_INDUCED) != 0;
     r.pack = (o->flags & GSM_MATCH_PACK_FRONTIER) != 0;
@@ -339,6 +341,31 @@ struct Matcher {
         L.la_label[L.la_n] = lab;
         L.la_qbit[L.la_n] = (uint32_t)p.order[k];
         L.la_need[L.la_n] = need;
+        if (o.lookahead2 && g.loff) {
+          // neighbours per label of the later query vertex, largest first
+          const int uk = p.order[k];
+          std::vector<std::pair<uint32_t, int32_t>> by_label;
+          for (int v = 0; v < qh.q; ++v) {
+            if (!((qh.adj[uk] >> v) & 1)) continue;
+            auto it = std::find_if(by_label.begin(), by_label.end(),
+                                   [&](const std::pair<uint32_t, int32_t> &e) { return e.second == p.qlab[v]; });
+            if (it == by_label.end())
+              by_label.push_back({1u, p.qlab[v]});
+            else
+              ++it->first;
+          }
+          std::stable_sort(by_label.begin(), by_label.end(),
+                           [](const std::pair<uint32_t, int32_t> &x, const std::pair<uint32_t, int32_t> &y) {
+                             return x.first > y.first;
+                           });
+          const int nl = std::min<int>((int)by_label.size(), kLa2Labels);
+          L.la2_n[L.la_n] = (uint8_t)nl;
+          for (int t = 0; t < nl; ++t) {
+            L.la2_label[L.la_n][t] = by_label[t].second;
+            L.la2_need[L.la_n][t] = by_label[t].first;
+          }
+          L.la2 = 1;
+        }
         ++L.la_n;
       }
     }

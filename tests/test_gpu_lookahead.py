@@ -109,3 +109,48 @@ def test_shapes_on_unlabelled_rmat_with_lookahead(name):
     c, _ = oracle.match(g, qr, rows=False, threads=NCPU)
     cg, _, _ = gsm.match(G, gsm.Query.from_workload(qr), lookahead=True)
     assert cg == c
+
+
+# --- two-step look-ahead (GSM_MATCH_LOOKAHEAD2) ---
+
+@pytest.mark.parametrize("seed", range(60))
+def test_random_instances_with_two_step_lookahead(seed):
+    rng = np.random.default_rng(79_000 + seed)
+    n = int(rng.integers(2, 48))
+    L = [1, 2, 3, 4, 0][seed % 5]
+    g = W.random_graph(n, float(rng.uniform(0.1, 0.6)), L, seed)
+    qr = W.random_query(int(rng.integers(2, 7)), float(rng.uniform(0, 0.6)), L, seed + 13)
+    G = gsm.Graph.from_workload(g, validate=True)
+    Q = gsm.Query.from_workload(qr)
+    kw = {} if oracle.match(g, qr, rows=False)[0] <= 300_000 else {"root": (0, 64, seed % 64)}
+    c, r = oracle.match(g, qr, **kw)
+    cg, rg = sorted_rows(G, Q, lookahead2=True, filter_rounds=seed % 3, **kw)
+    assert cg == c
+    np.testing.assert_array_equal(rg, r)
+
+
+@pytest.mark.parametrize("k", range(0, 20, 2))
+def test_powerlaw_slices_with_two_step_lookahead(powerlaw, k):
+    w, G = powerlaw
+    qr = w.queries[k]
+    Q = gsm.Query.from_workload(qr)
+    root = ((k + 1) % qr.q, 64, (k + 5) % 11)
+    c, _ = oracle.match(w.graph, qr, rows=False, threads=NCPU, root=root)
+    c2, _, s2 = gsm.match(G, Q, root=root, lookahead2=True)
+    c1, _, s1 = gsm.match(G, Q, root=root, lookahead=True)
+    print("powerlaw two-step slice", k, root, c, [s1["rows"][i] - s2["rows"][i] for i in range(qr.q)], flush=True)
+    assert c2 == c1 == c
+    for i in range(qr.q):
+        assert s2["rows"][i] <= s1["rows"][i]
+
+
+def test_two_step_lookahead_rows_small_budget(powerlaw):
+    w, G = powerlaw
+    qr = w.queries[4]
+    root = (0, 16, 3)
+    c, r = oracle.match(w.graph, qr, threads=NCPU, root=root)
+    Q = gsm.Query.from_workload(qr)
+    budget = gsm.min_budget(G, Q, host_rows=True) + (4 << 20)
+    cg, rg = sorted_rows(G, Q, root=root, lookahead2=True, budget=budget)
+    assert cg == c
+    np.testing.assert_array_equal(rg, r)
