@@ -113,6 +113,29 @@ def host_cores():
     return min(16, avail), os.cpu_count() or 1
 
 
+def oracle_queries_per_s(graph, queries, mod=64, budget_s=20.0):
+    """CPU baseline for the query-throughput workloads: the oracle, count
+    only, on all host threads it may use, over the queries in arrival order,
+    each on the root slice of residue k % mod of query vertex 0 (a 1/mod share
+    of its work), until budget_s seconds are spent; queries/s = slices done /
+    mod / seconds."""
+    import oracle
+    cores, nproc = host_cores()
+    t = time.perf_counter()
+    done = 0
+    for k, qr in enumerate(queries):
+        oracle.match(graph, qr, rows=False, threads=cores, root=(0, mod, k % mod))
+        done += 1
+        if time.perf_counter() - t > budget_s:
+            break
+    dt = time.perf_counter() - t
+    return {"value": round(done / mod / dt, 2), "unit": "queries/s", "cores": cores, "host_nproc": nproc,
+            "kind": "oracle",
+            "sample": "the first %d queries in arrival order, each on the root slice splitmix64(f(0)) %% %d == k %% %d "
+                      "(1/%d of its embeddings), count only, %.1f s; value = slices / %d / s"
+                      % (done, mod, mod, mod, dt, mod)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -488,6 +511,7 @@ def bench_batch(args):
         "per_launch_queries_per_s": round(qps_p, 1),
         "autotuned": best,
         "batched_over_per_launch": round(qps_b / qps_p, 3),
+        "cpu_baseline": None if args.no_cpu_baseline else oracle_queries_per_s(w.graph, w.queries),
     }
     print(json.dumps(out), flush=True)
 
@@ -537,8 +561,11 @@ def bench_serving(args):
         span = (max(r["t_done_ns"] for r in res) - min(r["t_submit_ns"] for r in res)) / 1e9
         return {"queries_per_s": round(len(res) / span, 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                 "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                "mean_batch": round(float(np.mean([r["batch_size"] for r in res])), 2)}
+                "mean_batch": round(float(np.mean([r["batch_size"] for r in res])), 2),
+                "arrivals": len(res), "rate_per_s": None if rate is None else round(rate, 1)}
 
+    cpu = None if args.no_cpu_baseline else oracle_queries_per_s(w.graph, w.queries)
+    log("cpu baseline: %s" % cpu)
     sat = run(None)
     log("saturation (all submitted at once): %s" % sat)
     r08 = run(0.8 * sat["queries_per_s"])
@@ -563,6 +590,7 @@ def bench_serving(args):
         "latency_at_0.8x_saturation": r08,
         "latency_at_0.5x_saturation": r05,
         "saturation": sat,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

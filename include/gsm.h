@@ -356,15 +356,19 @@ gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query_t *qs,
 /* ---------------------------------------------------------------- serving -- */
 
 /*
- * A serving engine over one resident graph: queries are submitted as they
- * arrive and matched (count only) by worker threads, each with its own HIP
- * stream and workspace, so batches of different workers overlap on the
- * device.  A free worker takes the oldest waiting queries that fit the device
- * memory still free (each query reserves its frontier estimate: its first
- * level's neighbour total for its second vertex's label times the row size,
- * clamped to [per_query_min, per_query_budget]) and matches them as one
- * batch; queries that arrive meanwhile join the next batch a worker forms.
- * The memory-bounded expansion keeps every query within its reservation.
+ * A serving engine over one resident graph (continuous batching): queries are
+ * submitted as they arrive and counted by worker threads, each with its own
+ * HIP stream.  A worker keeps several batched runs in flight and advances
+ * them in turn one step at a time (a level's scan or one chunk's expansion);
+ * between any two steps it admits the oldest waiting queries that fit the
+ * device memory still free (each query reserves its frontier estimate: its
+ * first level's neighbour total for its second vertex's label times the row
+ * size, clamped to [what it needs alone, per_query_budget]) and starts them
+ * as a new run, queries of one size sharing launches.  A query whose level
+ * pairs pass batch_heavy_pairs leaves its run and continues in a run of its
+ * own, so one exploding query does not hold back the others.  Runs of
+ * different workers overlap on the device.  The memory-bounded expansion
+ * keeps every run within its reservation.
  */
 typedef struct gsm_server_opts {
   uint32_t struct_size;
@@ -381,7 +385,12 @@ typedef struct gsm_result {
   gsm_status status;
   uint64_t count;
   uint64_t t_submit_ns, t_admit_ns, t_done_ns; /* steady-clock nanoseconds */
-  int32_t batch_size;                          /* queries in the batch that ran it */
+  int32_t batch_size;                          /* queries in the run that finished it */
+  int32_t worker;                              /* worker (stream) that ran it */
+  double dev_start_ms, dev_end_ms;             /* device time of its run's first and last work, in ms
+                                                  since gsm_server_create (HIP events on the worker's
+                                                  stream; runs of different workers that overlap in
+                                                  these times ran on the device at the same time) */
 } gsm_result;
 
 void gsm_server_opts_init(gsm_server_opts *o);

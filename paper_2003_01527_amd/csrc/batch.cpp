@@ -133,7 +133,7 @@ struct BatchMatcher {
     d_fb = reinterpret_cast<FirstBatch *>(base + o_fb);
     ws.counts.reserve((nq + 1) * sizeof(uint64_t), s);
     d_counts = ws.counts.as<uint64_t>();
-    GSM_HIP(hipMemsetAsync(d_counts, 0, (nq + 1) * sizeof(uint64_t), s));
+    launch_zero_u64(d_counts, nq + 1, s);
   }
 
   void plan_capacity() {
@@ -191,7 +191,7 @@ struct BatchMatcher {
       ws.evicted.reserve(nq + 1, s);
       h_qpairs.resize(nq + 1);
       if (evicted.size() != (size_t)nq + 1) evicted.assign(nq + 1, 0);
-      GSM_HIP(hipMemsetAsync(ws.qpairs.ptr, 0, (nq + 1) * sizeof(uint64_t), s));
+      launch_zero_u64(ws.qpairs.as<uint64_t>(), nq + 1, s);
       launch_query_pairs(ws.W[i].as<uint32_t>(), ws.qid[i].as<uint16_t>(), dcnt + kCntRows + i, cap[i],
                          ws.qpairs.as<uint64_t>(), s);
       GSM_HIP(hipMemcpyAsync(h_qpairs.data(), ws.qpairs.ptr, (nq + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost,
@@ -214,16 +214,18 @@ struct BatchMatcher {
                             ws.evicted.as<uint8_t>(), (uint16_t)nq, s);
   }
 
-  void process_level(int i) {
-    evict_heavy(i);
-    launch_scan(ws.W[i].as<uint32_t>(), dcnt + kCntRows + i, ws.S[i].as<uint64_t>(), dcnt + kCntPairs + i,
-                ws.scan_scratch.as<uint64_t>(), s);
-    fetch_counters();
-    const uint64_t N = ws.h_counters[kCntRows + i];
-    const uint64_t P = ws.h_counters[kCntPairs + i];
-    level_rows[i] += N;
-    level_pairs[i] += P;
-    if (P == 0) return;
+  // The levels still to expand, deepest last: depth-first over chunks (a
+  // chunk's rows are expanded to the end before the next chunk of the same
+  // level overwrites them), breadth-first inside a chunk.
+  struct Frame {
+    int i;                 // rows of level i (i matched vertices) are in ws.*[i]
+    bool counted = false;  // N and P read back
+    uint64_t N = 0, P = 0;
+    uint64_t b = 0;        // next pair of the level's range to expand
+  };
+  std::vector<Frame> stack;
+
+  ExpandArgs level_args(int i, uint64_t N) const {
     ExpandArgs a;
     std::memset(&a, 0, sizeof(a));
     a.g = dg;
@@ -240,33 +242,78 @@ struct BatchMatcher {
     a.counts = d_counts;
     a.probes = dcnt + kCntProbes;
     a.stage_out_ok = 1;
-    const bool deepest = (i + 1 >= maxq);  // every query of the batch has maxq vertices
-    const uint64_t c = deepest ? P : cap[i + 1];
-    for (uint64_t b = 0; b < P; b += c) {
-      const uint64_t e = std::min(P, b + c);
-      if (!deepest) {
-        reserve_level(i + 1, e - b);
-        a.rows_out = ws.rows[i + 1].as<int32_t>();
-        a.W_out = ws.W[i + 1].as<uint32_t>();
-        a.apos_out = ws.apos[i + 1].as<uint8_t>();
-        a.abase_out = ws.abase[i + 1].as<int64_t>();
-        a.qid_out = ws.qid[i + 1].as<uint16_t>();
-      }
-      GSM_HIP(hipMemsetAsync(dcnt + kCntRows + i + 1, 0, sizeof(uint64_t), s));
-      a.counter = dcnt + kCntRows + i + 1;
-      a.pair_begin = b;
-      a.pair_end = e;
-      launch_expand(a, deepest ? kModeBatchLast : kModeBatch, wg, items, s);
-      ++launches;
-      if (!deepest) process_level(i + 1);
+    return a;
+  }
+
+  // First frontier of every query; the level-by-level work is then done by step().
+  void start() {
+    upload_tables();
+    launch_zero_u64(dcnt, 64, s);
+    reserve_level(1, cap[1]);
+    launch_compact_first_batch(dg, d_fb, nq, ws.rows[1].as<int32_t>(),
+                               ws.qid[1].as<uint16_t>(), ws.W[1].as<uint32_t>(), ws.abase[1].as<int64_t>(),
+                               ws.apos[1].as<uint8_t>(), dcnt + kCntRows + 1, d_counts, nullptr, s);
+    stack.clear();
+    if (maxq > 1) stack.push_back(Frame{1});
+  }
+
+  // One unit of work: the scan of a level and its read-back, or one chunk's
+  // expansion launch.  Returns false once every level is done.
+  bool step() {
+    if (stack.empty()) return false;
+    Frame &f = stack.back();
+    const int i = f.i;
+    if (!f.counted) {
+      evict_heavy(i);
+      launch_scan(ws.W[i].as<uint32_t>(), dcnt + kCntRows + i, ws.S[i].as<uint64_t>(), dcnt + kCntPairs + i,
+                  ws.scan_scratch.as<uint64_t>(), s);
+      fetch_counters();
+      f.N = ws.h_counters[kCntRows + i];
+      f.P = ws.h_counters[kCntPairs + i];
+      f.counted = true;
+      level_rows[i] += f.N;
+      level_pairs[i] += f.P;
+      if (f.P == 0) stack.pop_back();
+      return !stack.empty();
     }
+    if (f.b >= f.P) {
+      stack.pop_back();
+      return !stack.empty();
+    }
+    const bool deepest = (i + 1 >= maxq);  // every query of the batch has maxq vertices
+    const uint64_t c = deepest ? f.P : cap[i + 1];
+    const uint64_t b = f.b, e = std::min(f.P, b + c);
+    f.b = e;
+    ExpandArgs a = level_args(i, f.N);
+    if (!deepest) {
+      reserve_level(i + 1, e - b);
+      a.rows_out = ws.rows[i + 1].as<int32_t>();
+      a.W_out = ws.W[i + 1].as<uint32_t>();
+      a.apos_out = ws.apos[i + 1].as<uint8_t>();
+      a.abase_out = ws.abase[i + 1].as<int64_t>();
+      a.qid_out = ws.qid[i + 1].as<uint16_t>();
+    }
+    launch_zero_u64(dcnt + kCntRows + i + 1, 1, s);
+    a.counter = dcnt + kCntRows + i + 1;
+    a.pair_begin = b;
+    a.pair_end = e;
+    launch_expand(a, deepest ? kModeBatchLast : kModeBatch, wg, items, s);
+    ++launches;
+    if (!deepest) stack.push_back(Frame{i + 1});  // invalidates f
+    return true;
+  }
+
+  // Per-query counts once step() has returned false (waits for the stream).
+  void finish(uint64_t *counts) {
+    GSM_HIP(hipMemcpyAsync(counts, d_counts, nq * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    sync();
   }
 
   // First-level (row, neighbour) pairs of every query, from the first-frontier
   // kernel in estimate mode (nothing is written but the totals).
   std::vector<uint64_t> first_level_pairs() {
     upload_tables();
-    GSM_HIP(hipMemsetAsync(d_counts, 0, std::max(nq, 1) * sizeof(uint64_t), s));
+    launch_zero_u64(d_counts, std::max(nq, 1), s);
     launch_compact_first_batch(dg, d_fb, nq, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                nullptr, d_counts, s);
     std::vector<uint64_t> out(nq);
@@ -276,19 +323,45 @@ struct BatchMatcher {
   }
 
   void run(uint64_t *counts) {
-    upload_tables();
-    GSM_HIP(hipMemsetAsync(dcnt, 0, 64 * sizeof(uint64_t), s));
-    reserve_level(1, cap[1]);
-    launch_compact_first_batch(dg, d_fb, nq, ws.rows[1].as<int32_t>(),
-                               ws.qid[1].as<uint16_t>(), ws.W[1].as<uint32_t>(), ws.abase[1].as<int64_t>(),
-                               ws.apos[1].as<uint8_t>(), dcnt + kCntRows + 1, d_counts, nullptr, s);
-    if (maxq > 1) process_level(1);
-    GSM_HIP(hipMemcpyAsync(counts, d_counts, nq * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    sync();
+    start();
+    while (step()) {
+    }
+    finish(counts);
   }
 };
 
 }  // namespace
+
+struct BatchRun::Impl {
+  BatchMatcher m;
+  Impl(gsm_graph &g, const gsm_query *const *qs, int nq, Workspace &ws, hipStream_t s, const RootSlice *sl)
+      : m(g, qs, nq, ws, s, sl) {}
+};
+
+BatchRun::BatchRun(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_match_opts &o, Workspace &ws,
+                   const RootSlice *slices, uint64_t evict_pairs)
+    : impl(new Impl(g, qs, nq, ws, (hipStream_t)o.hip_stream, slices)) {
+  BatchMatcher &m = impl->m;
+  m.rounds = o.filter_rounds;
+  m.use_deg = o.use_degree;
+  m.use_ne = o.use_ne;
+  m.wg = o.wg_size ? o.wg_size : 512;
+  m.items = o.tile_items ? o.tile_items : 4;
+  m.budget = o.memory_budget_bytes ? o.memory_budget_bytes : (uint64_t(4) << 30);
+  m.evict_pairs = evict_pairs;
+  m.plan_capacity();
+  m.start();
+}
+
+BatchRun::~BatchRun() = default;
+
+bool BatchRun::step() { return impl->m.step(); }
+
+void BatchRun::finish(uint64_t *counts, std::vector<uint8_t> &evicted) {
+  impl->m.finish(counts);
+  evicted.assign(impl->m.nq, 0);
+  for (int k = 0; k < impl->m.nq && k < (int)impl->m.evicted.size(); ++k) evicted[k] = impl->m.evicted[k];
+}
 
 void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_match_opts &o,
                     Workspace &ws, uint64_t *counts, uint64_t *launches_out, gsm_stats *st,

@@ -341,6 +341,25 @@ gsm_status match_call(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts,
 // restricted to the root slice rs.
 uint64_t match_count_one(gsm_graph &g, const gsm_query &q, const gsm_match_opts &o, Workspace &ws,
                          const RootSlice &rs);
+// A batched match (queries of one size) advanced one step at a time by its
+// caller: a step is one level's scan and read-back or one chunk's expansion,
+// so the serving engine can interleave the steps of several runs and start
+// new arrivals between them.  Memory comes from ws within o's budget.
+class BatchRun {
+ public:
+  BatchRun(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_match_opts &o, Workspace &ws,
+           const RootSlice *slices, uint64_t evict_pairs);
+  ~BatchRun();
+  bool step();  // false once every level is done
+  // Counts after the last step (waits for the stream); evicted[k] != 0 when
+  // query k left the shared launches (its count is then not valid here).
+  void finish(uint64_t *counts, std::vector<uint8_t> &evicted);
+
+ private:
+  struct Impl;
+  std::unique_ptr<Impl> impl;
+};
+
 // Smallest budget gsm_match accepts for a query of q vertices, count only.
 uint64_t min_budget_bytes_single(int64_t n, int q);
 // Smallest batched budget for nq queries of q vertices (first frontiers at

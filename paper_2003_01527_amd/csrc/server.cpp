@@ -1,12 +1,16 @@
 // Serving engine: a resident graph, an arrival queue, memory-based admission
-// and worker threads that each match one batch at a time on their own stream
-// and workspace, so batches of different workers overlap on the device and
-// queries that arrive while others run join the next batch a worker forms.
+// and worker threads, each with its own HIP stream.  A worker keeps several
+// batched runs in flight and advances them one step at a time (a level's scan
+// or one chunk's expansion), taking newly arrived queries into a new run
+// between any two steps: a query that arrives while others are on the GPU
+// starts at the next step instead of after the running batch.  Runs of
+// different workers overlap on the device.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <thread>
 #include <unordered_map>
 
@@ -29,6 +33,19 @@ struct Request {
   bool done = false;
 };
 
+// One batched run in a worker: queries of one size (or one query moved out
+// of a shared run), its workspace and the events that time it on the device.
+struct Run {
+  std::vector<Request *> reqs;
+  std::vector<const gsm_query *> qs;
+  std::vector<gsm::RootSlice> slices;
+  std::unique_ptr<gsm::Workspace> ws;
+  std::unique_ptr<gsm::BatchRun> br;
+  uint64_t budget = 0;
+  bool solo = false;
+  hipEvent_t ev_start = nullptr, ev_end = nullptr;
+};
+
 }  // namespace
 
 struct gsm_server {
@@ -45,6 +62,7 @@ struct gsm_server {
   bool stopping = false;
   std::vector<std::thread> workers;
   std::string worker_error;
+  hipEvent_t ev_ref = nullptr;  // device-time origin of gsm_result's device times
 
   // Frontier estimate of a query: the first level's (row, neighbour) pairs
   // are at most the degree total of its first vertex's label class; each
@@ -54,8 +72,7 @@ struct gsm_server {
     const int32_t l0 = p.qlab[p.order[0]];
     const uint64_t pairs = (l0 >= 0 && (size_t)l0 < label_deg.size()) ? label_deg[l0] : 0;
     const uint64_t row2 = 4 * 2 + 23;
-    // the smallest budget either driver accepts for this query alone (a batch
-    // of one, or the single-query path a heavy query is moved to)
+    // the smallest budget the batched driver accepts for this query alone
     const uint64_t floor = std::max(gsm::min_budget_bytes_batch(*g, 1, p.q), gsm::min_budget_bytes_single(g->n, p.q));
     uint64_t est = pairs * row2 + floor;
     est = std::max<uint64_t>(est, floor + (uint64_t(64) << 20));
@@ -69,85 +86,200 @@ struct gsm_server {
     return reserved + r->reserve <= o.arena_bytes || reserved == 0;  // an oversize query runs alone
   }
 
-  void worker_main(int wid) {
+  struct Worker {
+    gsm_server *srv;
+    int id;
     hipStream_t stream = nullptr;
-    gsm::Workspace *ws = nullptr;
-    try {
-      GSM_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
-      ws = new gsm::Workspace();
-    } catch (const gsm::Error &e) {
-      std::lock_guard<std::mutex> lk(mu);
-      worker_error = e.msg;
-      return;
+    std::vector<std::unique_ptr<Run>> runs;
+    std::vector<std::unique_ptr<gsm::Workspace>> ws_pool;
+    std::vector<hipEvent_t> ev_pool;
+
+    hipEvent_t event() {
+      if (!ev_pool.empty()) {
+        hipEvent_t e = ev_pool.back();
+        ev_pool.pop_back();
+        return e;
+      }
+      hipEvent_t e;
+      GSM_HIP(hipEventCreate(&e));
+      return e;
     }
-    for (;;) {
-      std::vector<Request *> batch;
-      uint64_t budget = 0;
-      {
-        std::unique_lock<std::mutex> lk(mu);
-        // sleep until the oldest waiting request can be admitted (it fits the
-        // free arena, or nothing is running so it may run alone, and a slot
-        // is free) or the server stops; a finishing batch wakes the workers
-        cv_work.wait(lk, [&] { return (stopping && pending.empty()) || admissible(); });
-        if (pending.empty() && stopping) break;
-        // admit the oldest requests that fit the free arena
-        while (!pending.empty() && (int)batch.size() < o.max_batch && admissible()) {
-          Request *r = pending.front();
-          pending.pop_front();
-          reserved += r->reserve;
-          budget += r->reserve;
-          ++active;
-          r->res.t_admit_ns = now_ns();
-          batch.push_back(r);
+
+    std::unique_ptr<gsm::Workspace> workspace() {
+      if (!ws_pool.empty()) {
+        auto w = std::move(ws_pool.back());
+        ws_pool.pop_back();
+        return w;
+      }
+      return std::unique_ptr<gsm::Workspace>(new gsm::Workspace());
+    }
+
+    gsm_match_opts match_opts(uint64_t budget) const {
+      gsm_match_opts mo;
+      gsm_match_opts_init(&mo);
+      mo.hip_stream = stream;
+      mo.memory_budget_bytes = budget;
+      mo.wg_size = srv->o.wg_size;
+      mo.tile_items = srv->o.tile_items;
+      return mo;
+    }
+
+    // Starts a run over reqs (first frontier launched); on an error the
+    // requests are finished with it.
+    void start_run(std::vector<Request *> reqs, bool solo) {
+      std::unique_ptr<Run> r(new Run());
+      r->reqs = std::move(reqs);
+      r->solo = solo;
+      for (Request *q : r->reqs) {
+        r->qs.push_back(&q->q);
+        r->slices.push_back(q->slice);
+        r->budget += q->reserve;
+      }
+      try {
+        r->ws = workspace();
+        r->ev_start = event();
+        r->ev_end = event();
+        GSM_HIP(hipEventRecord(r->ev_start, stream));
+        const uint64_t heavy = srv->o.batch_heavy_pairs ? srv->o.batch_heavy_pairs : (uint64_t(1) << 18);
+        const uint64_t evict = (solo || heavy == UINT64_MAX) ? 0 : heavy;
+        r->br.reset(new gsm::BatchRun(*srv->g, r->qs.data(), (int)r->qs.size(), match_opts(r->budget), *r->ws,
+                                      r->slices.data(), evict));
+        runs.push_back(std::move(r));
+      } catch (const gsm::Error &e) {
+        complete(*r, e.status, e.msg, nullptr, nullptr);
+        recycle(*r);
+      } catch (const std::bad_alloc &) {
+        complete(*r, GSM_E_OOM, "host allocation failed", nullptr, nullptr);
+        recycle(*r);
+      }
+    }
+
+    void recycle(Run &r) {
+      (void)hipStreamSynchronize(stream);  // no launch of this run may still use its workspace
+      r.br.reset();
+      if (r.ws) ws_pool.push_back(std::move(r.ws));
+      if (r.ev_start) ev_pool.push_back(r.ev_start);
+      if (r.ev_end) ev_pool.push_back(r.ev_end);
+      r.ev_start = r.ev_end = nullptr;
+    }
+
+    // Posts the results of the requests of r that are finished (all but
+    // those in moved_out, which continue in runs of their own).
+    void complete(Run &r, gsm_status st, const std::string &err, const uint64_t *counts,
+                  const std::vector<uint8_t> *moved_out) {
+      double t0 = 0, t1 = 0;
+      if (st == GSM_OK && r.ev_start && r.ev_end) {
+        float a = 0, b = 0;
+        if (hipEventElapsedTime(&a, srv->ev_ref, r.ev_start) == hipSuccess &&
+            hipEventElapsedTime(&b, srv->ev_ref, r.ev_end) == hipSuccess) {
+          t0 = a;
+          t1 = b;
         }
       }
-      std::vector<const gsm_query *> qs;
-      std::vector<gsm::RootSlice> slices;
-      for (Request *r : batch) {
-        qs.push_back(&r->q);
-        slices.push_back(r->slice);
+      {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        const uint64_t t = now_ns();
+        for (size_t k = 0; k < r.reqs.size(); ++k) {
+          if (moved_out && k < moved_out->size() && (*moved_out)[k]) continue;
+          Request *q = r.reqs[k];
+          q->res.status = st;
+          q->res.count = counts ? counts[k] : 0;
+          q->res.t_done_ns = t;
+          q->res.batch_size = (int32_t)r.reqs.size();
+          q->res.worker = id;
+          q->res.dev_start_ms = t0;
+          q->res.dev_end_ms = t1;
+          q->done = true;
+          srv->reserved -= q->reserve;
+          --srv->active;
+        }
+        if (st != GSM_OK && srv->worker_error.empty()) srv->worker_error = err;
       }
-      std::vector<uint64_t> counts(batch.size(), 0);
+      srv->cv_done.notify_all();
+      srv->cv_work.notify_all();
+    }
+
+    // Advances run k by one step; when it has finished, posts its results,
+    // starts a run of its own for every query it moved out and returns true.
+    bool advance(size_t k) {
+      Run &r = *runs[k];
+      bool more = false;
       gsm_status st = GSM_OK;
       std::string err;
       try {
-        gsm_match_opts mo;
-        gsm_match_opts_init(&mo);
-        mo.hip_stream = stream;
-        mo.memory_budget_bytes = budget;
-        mo.wg_size = o.wg_size;
-        mo.tile_items = o.tile_items;
-        mo.batch_heavy_pairs = o.batch_heavy_pairs;
-        gsm::match_batch_on(*g, qs.data(), (int)qs.size(), mo, *ws, counts.data(), nullptr, nullptr,
-                            slices.data());
+        more = r.br->step();
       } catch (const gsm::Error &e) {
         st = e.status;
         err = e.msg;
       } catch (const std::bad_alloc &) {
         st = GSM_E_OOM;
+        err = "host allocation failed";
       }
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        const uint64_t t = now_ns();
-        for (size_t k = 0; k < batch.size(); ++k) {
-          Request *r = batch[k];
-          r->res.status = st;
-          r->res.count = counts[k];
-          r->res.t_done_ns = t;
-          r->res.batch_size = (int32_t)batch.size();
-          r->done = true;
-          reserved -= r->reserve;
-          --active;
+      if (more && st == GSM_OK) return false;
+      std::vector<uint64_t> counts(r.reqs.size(), 0);
+      std::vector<uint8_t> moved;
+      if (st == GSM_OK) {
+        try {
+          GSM_HIP(hipEventRecord(r.ev_end, stream));
+          r.br->finish(counts.data(), moved);
+        } catch (const gsm::Error &e) {
+          st = e.status;
+          err = e.msg;
+          moved.clear();
         }
-        if (st != GSM_OK && worker_error.empty()) worker_error = err;
       }
-      cv_done.notify_all();
-      cv_work.notify_all();
+      complete(r, st, err, counts.data(), &moved);
+      std::vector<Request *> alone;
+      for (size_t j = 0; j < moved.size(); ++j)
+        if (moved[j]) alone.push_back(r.reqs[j]);
+      recycle(r);
+      runs.erase(runs.begin() + k);
+      for (Request *q : alone) start_run({q}, true);
+      return true;
     }
-    delete ws;
-    (void)hipStreamDestroy(stream);
-    (void)wid;
-  }
+
+    void main() {
+      try {
+        GSM_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+      } catch (const gsm::Error &e) {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->worker_error = e.msg;
+        return;
+      }
+      size_t next = 0;
+      for (;;) {
+        std::vector<Request *> admitted;
+        {
+          std::unique_lock<std::mutex> lk(srv->mu);
+          // idle: sleep until the oldest waiting request can be admitted (it
+          // fits the free arena, or nothing runs so it may run alone, and a
+          // slot is free) or the server stops; a finishing run wakes workers
+          if (runs.empty())
+            srv->cv_work.wait(lk, [&] { return (srv->stopping && srv->pending.empty()) || srv->admissible(); });
+          if (runs.empty() && srv->pending.empty() && srv->stopping) break;
+          // between two steps: admit the oldest requests that fit
+          while ((int)admitted.size() < srv->o.max_batch && srv->admissible()) {
+            Request *r = srv->pending.front();
+            srv->pending.pop_front();
+            srv->reserved += r->reserve;
+            ++srv->active;
+            r->res.t_admit_ns = now_ns();
+            admitted.push_back(r);
+          }
+        }
+        // the batched kernels share launches among queries of one size
+        std::map<int, std::vector<Request *>> by_size;
+        for (Request *r : admitted) by_size[r->q.q].push_back(r);
+        for (auto &kv : by_size) start_run(std::move(kv.second), false);
+        if (runs.empty()) continue;
+        next %= runs.size();
+        if (!advance(next)) ++next;  // a finished run was erased: the next one moved to its place
+      }
+      for (auto &w : ws_pool) w.reset();
+      for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+      (void)hipStreamDestroy(stream);
+    }
+  };
 };
 
 namespace gsm {
@@ -209,7 +341,18 @@ gsm_status gsm_server_create(gsm_graph_t g, const gsm_server_opts *opts, gsm_ser
     }
     for (int64_t v = 0; v < g->n; ++v) srv->label_deg[lab.empty() ? 0 : lab[v]] += (uint64_t)(rp[v + 1] - rp[v]);
   }
-  for (int w = 0; w < o.workers; ++w) srv->workers.emplace_back([srv, w] { srv->worker_main(w); });
+  if (hipEventCreate(&srv->ev_ref) != hipSuccess || hipEventRecord(srv->ev_ref, nullptr) != hipSuccess ||
+      hipEventSynchronize(srv->ev_ref) != hipSuccess) {
+    if (srv->ev_ref) (void)hipEventDestroy(srv->ev_ref);
+    delete srv;
+    gsm::set_error("gsm_server_create: device timing event failed");
+    return GSM_E_DEVICE;
+  }
+  for (int w = 0; w < o.workers; ++w)
+    srv->workers.emplace_back([srv, w] {
+      gsm_server::Worker wk{srv, w};
+      wk.main();
+    });
   *out = srv;
   return GSM_OK;
 }
@@ -295,6 +438,7 @@ void gsm_server_destroy(gsm_server_t srv) {
   srv->cv_work.notify_all();
   for (auto &t : srv->workers) t.join();
   for (auto &kv : srv->all) delete kv.second;
+  if (srv->ev_ref) (void)hipEventDestroy(srv->ev_ref);
   delete srv;
 }
 

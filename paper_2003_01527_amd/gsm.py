@@ -358,7 +358,8 @@ class ServerOpts(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("count", ctypes.c_uint64), ("t_submit_ns", ctypes.c_uint64),
                 ("t_admit_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64),
-                ("batch_size", ctypes.c_int32)]
+                ("batch_size", ctypes.c_int32), ("worker", ctypes.c_int32),
+                ("dev_start_ms", ctypes.c_double), ("dev_end_ms", ctypes.c_double)]
 
 
 class Server:
@@ -391,7 +392,8 @@ class Server:
         r = Result()
         _check(_load().gsm_server_wait(self._h, ticket, timeout_ms, ctypes.byref(r)))
         return {"count": int(r.count), "t_submit_ns": int(r.t_submit_ns), "t_admit_ns": int(r.t_admit_ns),
-                "t_done_ns": int(r.t_done_ns), "batch_size": int(r.batch_size)}
+                "t_done_ns": int(r.t_done_ns), "batch_size": int(r.batch_size), "worker": int(r.worker),
+                "dev_start_ms": float(r.dev_start_ms), "dev_end_ms": float(r.dev_end_ms)}
 
     def close(self):
         if self._h:

@@ -32,16 +32,47 @@ def test_results_equal_alone(setup, workers, arena):
         assert 1 <= r["batch_size"] <= 16
 
 
-def test_batches_overlap_on_device(setup):
-    """With two workers, some request of one batch runs while another batch runs."""
+def test_runs_of_different_workers_overlap_on_device(setup):
+    """Device time (HIP events on the workers' streams): some run of one
+    worker executes while a run of another worker executes."""
     w, G, Qs, alone = setup
     srv = gsm.Server(G, workers=2, max_batch=4)
     tickets = [(k, srv.submit(Qs[k])) for k in range(len(Qs))]
     res = [srv.wait(t) for _, t in tickets]
     srv.close()
-    spans = sorted({(r["t_admit_ns"], r["t_done_ns"]) for r in res})
-    overlap = any(b[0] < a[1] for a, b in zip(spans, spans[1:]))
+    for (k, _), r in zip(tickets, res):
+        assert r["count"] == alone[k]
+        assert 0 <= r["dev_start_ms"] <= r["dev_end_ms"]
+    spans = {wk: sorted({(r["dev_start_ms"], r["dev_end_ms"]) for r in res if r["worker"] == wk}) for wk in (0, 1)}
+    assert spans[0] and spans[1]
+    overlap = any(a0 < b1 and b0 < a1 for a0, a1 in spans[0] for b0, b1 in spans[1])
     assert overlap
+
+
+def test_arrivals_join_between_steps():
+    """One worker: light queries that arrive while a heavy query is being
+    expanded chunk by chunk start between its steps and finish before it,
+    inside its device-time span."""
+    import time
+    g = W.powerlaw_graph()
+    g.labels = None
+    G = gsm.Graph.from_workload(g)
+    heavy = gsm.Query.from_workload(W.shape("C4"))
+    light = gsm.Query.from_workload(W.shape("K2"))
+    c_heavy, c_light = gsm.match(G, heavy)[0], gsm.match(G, light)[0]
+    # a small per-query reservation cuts the heavy query into many chunks
+    srv = gsm.Server(G, workers=1, per_query_budget=24 << 20, batch_heavy_pairs=(1 << 64) - 1)
+    th = srv.submit(heavy)
+    time.sleep(0.05)
+    tl = [srv.submit(light) for _ in range(4)]
+    rh = srv.wait(th)
+    rl = [srv.wait(t) for t in tl]
+    srv.close()
+    assert rh["count"] == c_heavy and all(r["count"] == c_light for r in rl)
+    inside = [r for r in rl if r["t_done_ns"] < rh["t_done_ns"]]
+    assert inside, "no light query finished before the heavy one"
+    for r in inside:
+        assert rh["dev_start_ms"] <= r["dev_start_ms"] <= r["dev_end_ms"] <= rh["dev_end_ms"]
 
 
 def test_wait_timeout_and_unknown_ticket(setup):
