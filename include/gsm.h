@@ -364,9 +364,10 @@ gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query_t *qs,
  * device memory still free (each query reserves its frontier estimate: its
  * first level's neighbour total for its second vertex's label times the row
  * size, clamped to [what it needs alone, per_query_budget]) and starts them
- * as a new run, queries of one size sharing launches.  A query whose level
- * pairs pass batch_heavy_pairs leaves its run and continues in a run of its
- * own, so one exploding query does not hold back the others.  Runs of
+ * as a new run, queries of one size sharing launches (a run of one query
+ * uses the faster query-uniform kernels of gsm_match).  A query whose level
+ * pairs pass batch_heavy_pairs leaves its shared run and continues in a run
+ * of its own, so one exploding query does not hold back the others.  Runs of
  * different workers overlap on the device.  The memory-bounded expansion
  * keeps every run within its reservation.
  */

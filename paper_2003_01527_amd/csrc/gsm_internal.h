@@ -345,20 +345,31 @@ uint64_t match_count_one(gsm_graph &g, const gsm_query &q, const gsm_match_opts 
 // caller: a step is one level's scan and read-back or one chunk's expansion,
 // so the serving engine can interleave the steps of several runs and start
 // new arrivals between them.  Memory comes from ws within o's budget.
-class BatchRun {
+class StepRun {
+ public:
+  virtual ~StepRun() = default;
+  virtual bool step() = 0;  // false once every level is done
+  // Counts after the last step (waits for the stream); moved[k] != 0 when
+  // query k left the shared launches (its count is then not valid here).
+  virtual void finish(uint64_t *counts, std::vector<uint8_t> &moved) = 0;
+};
+
+class BatchRun : public StepRun {
  public:
   BatchRun(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_match_opts &o, Workspace &ws,
            const RootSlice *slices, uint64_t evict_pairs);
-  ~BatchRun();
-  bool step();  // false once every level is done
-  // Counts after the last step (waits for the stream); evicted[k] != 0 when
-  // query k left the shared launches (its count is then not valid here).
-  void finish(uint64_t *counts, std::vector<uint8_t> &evicted);
+  ~BatchRun() override;
+  bool step() override;
+  void finish(uint64_t *counts, std::vector<uint8_t> &moved) override;
 
  private:
   struct Impl;
   std::unique_ptr<Impl> impl;
 };
+
+// One query, count only, on the query-uniform kernels, step by step.
+std::unique_ptr<StepRun> make_single_count_run(gsm_graph &g, const gsm_query &q, const gsm_match_opts &o,
+                                               Workspace &ws, const RootSlice &rs);
 
 // Smallest budget gsm_match accepts for a query of q vertices, count only.
 uint64_t min_budget_bytes_single(int64_t n, int q);

@@ -393,17 +393,20 @@ struct Matcher {
     host_rows_done += nrows;
   }
 
-  // rows of level i (i matched vertices) are in ws.*[i], their count in dcnt[i]
-  void process_level(int i) {
-    launch_scan(ws.W[i].as<uint32_t>(), dcnt + kCntRows + i, ws.S[i].as<uint64_t>(),
-                dcnt + kCntPairs + i, ws.scan_scratch.as<uint64_t>(), s);
-    fetch_counters();
-    const uint64_t N = ws.h_counters[kCntRows + i];
-    const uint64_t P = ws.h_counters[kCntPairs + i];
-    st.rows[i - 1] += N;
-    st.pairs[i] += P;
-    if (P == 0) return;
-    const bool last = (i == p.q - 1);
+  // The levels still to expand, deepest last: depth-first over chunks (a
+  // chunk's rows are expanded to the end before the next chunk of the same
+  // level overwrites them), breadth-first inside a chunk.  Rows of level i
+  // (i matched vertices) are in ws.*[i], their number in dcnt[kCntRows + i].
+  struct Frame {
+    int i;
+    bool counted = false;  // N and P read back
+    uint64_t N = 0, P = 0;
+    uint64_t b = 0;        // next pair of the level's range to expand
+  };
+  std::vector<Frame> stack;
+  uint64_t single_count = 0;  // q == 1: the candidates, counted in start()
+
+  ExpandArgs level_expand_args(int i, uint64_t N) const {
     ExpandArgs a;
     std::memset(&a, 0, sizeof(a));
     a.g = dg;
@@ -417,25 +420,13 @@ struct Matcher {
     a.pack_bits = pack_bits;
     a.pack_in = packed[i] ? 1 : 0;
     a.pack_out = (i + 1 < p.q && packed[i + 1]) ? 1 : 0;
-    if (!last) {
-      const uint64_t c = cap[i + 1];
-      for (uint64_t b = 0; b < P && !cancelled; b += c) {
-        const uint64_t e = std::min(P, b + c);
-        reserve_level(i + 1, e - b);
-        zero_counter(kCntRows + i + 1);
-        a.pair_begin = b;
-        a.pair_end = e;
-        a.rows_out = ws.rows[i + 1].as<int32_t>();
-        a.W_out = ws.W[i + 1].as<uint32_t>();
-        a.apos_out = ws.apos[i + 1].as<uint8_t>();
-        a.abase_out = ws.abase[i + 1].as<int64_t>();
-        a.counter = dcnt + kCntRows + i + 1;
-        expand(a, kModeNext);
-        st.chunks[i]++;
-        process_level(i + 1);
-      }
-      return;
-    }
+    return a;
+  }
+
+  // The last level, all of it: count, rows straight to the caller's device
+  // buffer, or chunks through the staging buffer to the host.
+  void last_level(int i, uint64_t N, uint64_t P) {
+    ExpandArgs a = level_expand_args(i, N);
     a.counter = dcnt + kCntResult;
     if (!rows_user && !o.emit) {  // count only
       a.pair_begin = 0;
@@ -467,9 +458,56 @@ struct Matcher {
     }
   }
 
-  uint64_t run() {
+  // One unit of work: a level's scan and read-back, one chunk's expansion
+  // to the next level, or the whole last level.  Returns false when done.
+  bool step() {
+    if (stack.empty() || cancelled) return false;
+    Frame &f = stack.back();
+    const int i = f.i;
+    if (!f.counted) {
+      launch_scan(ws.W[i].as<uint32_t>(), dcnt + kCntRows + i, ws.S[i].as<uint64_t>(),
+                  dcnt + kCntPairs + i, ws.scan_scratch.as<uint64_t>(), s);
+      fetch_counters();
+      f.N = ws.h_counters[kCntRows + i];
+      f.P = ws.h_counters[kCntPairs + i];
+      f.counted = true;
+      st.rows[i - 1] += f.N;
+      st.pairs[i] += f.P;
+      if (f.P == 0) stack.pop_back();
+      return !stack.empty();
+    }
+    if (i == p.q - 1) {
+      last_level(i, f.N, f.P);
+      stack.pop_back();
+      return !stack.empty() && !cancelled;
+    }
+    if (f.b >= f.P) {
+      stack.pop_back();
+      return !stack.empty();
+    }
+    const uint64_t b = f.b, e = std::min(f.P, b + cap[i + 1]);
+    f.b = e;
+    ExpandArgs a = level_expand_args(i, f.N);
+    reserve_level(i + 1, e - b);
+    zero_counter(kCntRows + i + 1);
+    a.pair_begin = b;
+    a.pair_end = e;
+    a.rows_out = ws.rows[i + 1].as<int32_t>();
+    a.W_out = ws.W[i + 1].as<uint32_t>();
+    a.apos_out = ws.apos[i + 1].as<uint8_t>();
+    a.abase_out = ws.abase[i + 1].as<int64_t>();
+    a.counter = dcnt + kCntRows + i + 1;
+    expand(a, kModeNext);
+    st.chunks[i]++;
+    stack.push_back(Frame{i + 1});  // invalidates f
+    return true;
+  }
+
+  // Filter and first frontier; step() then expands level by level.
+  void start() {
     launch_zero_u64(dcnt, 64, s);
     filter();
+    stack.clear();
     const int q = p.q;
     const uint32_t qbit0 = (uint32_t)p.order[0];
     if (q == 1) {
@@ -489,22 +527,34 @@ struct Matcher {
       launch_compact_first(dg, ws.cmask.as<uint16_t>(), qbit0, 0, nullptr, nullptr, nullptr, nullptr,
                            dcnt + kCntResult, dst, dcap, s);
       fetch_counters();
-      const uint64_t count = ws.h_counters[kCntResult];
-      st.rows[0] = count;
-      st.candidates_root = count;
-      if (emit_host) drain_stage(count);
-      return count;
+      single_count = ws.h_counters[kCntResult];
+      st.rows[0] = single_count;
+      st.candidates_root = single_count;
+      if (emit_host) drain_stage(single_count);
+      return;
     }
     reserve_level(1, (uint64_t)std::max<int64_t>(g.n, 1));
     launch_compact_first(dg, ws.cmask.as<uint16_t>(), qbit0, p.qlab[p.order[1]],
                          ws.rows[1].as<int32_t>(), ws.W[1].as<uint32_t>(), ws.abase[1].as<int64_t>(),
                          ws.apos[1].as<uint8_t>(), dcnt + kCntRows + 1, nullptr, 0, s);
-    process_level(1);
+    stack.push_back(Frame{1});
+  }
+
+  // The count once step() has returned false (waits for the stream).
+  uint64_t finish() {
+    if (p.q == 1) return single_count;
     fetch_counters();
     st.candidates_root = st.rows[0];
     st.probes = ws.h_counters[kCntProbes];
-    st.rows[q - 1] = ws.h_counters[kCntResult];
+    st.rows[p.q - 1] = ws.h_counters[kCntResult];
     return ws.h_counters[kCntResult];
+  }
+
+  uint64_t run() {
+    start();
+    while (step()) {
+    }
+    return finish();
   }
 
   // Algorithmic bytes of the expansion launches (what the method must move),
@@ -561,6 +611,39 @@ Workspace &acquire_ws(gsm_graph &g) {
 }  // namespace
 
 uint64_t min_budget_bytes_single(int64_t n, int q) { return min_budget_bytes(n, q, false); }
+
+namespace {
+// One query, count only, advanced step by step (the query-uniform kernels).
+class SingleCountRun : public StepRun {
+ public:
+  SingleCountRun(gsm_graph &g, const gsm_query &q, const Options &o, Workspace &ws) : m(g, q, o, ws) {
+    m.plan_capacity();
+    m.start();
+  }
+  bool step() override { return m.step(); }
+  void finish(uint64_t *counts, std::vector<uint8_t> &moved) override {
+    counts[0] = m.finish();
+    moved.assign(1, 0);
+  }
+
+ private:
+  Matcher m;
+};
+}  // namespace
+
+std::unique_ptr<StepRun> make_single_count_run(gsm_graph &g, const gsm_query &q, const gsm_match_opts &oo,
+                                               Workspace &ws, const RootSlice &rs) {
+  gsm_match_opts plain = oo;
+  plain.root_qvertex = rs.qvertex;
+  plain.root_mod = rs.qvertex >= 0 ? rs.mod : 0;
+  plain.root_rem = rs.qvertex >= 0 ? rs.rem : 0;
+  Options o = read_opts(&plain, q.q);
+  o.emit = nullptr;
+  o.emit_ctx = nullptr;
+  o.rows_dev = false;
+  o.stats = nullptr;
+  return std::unique_ptr<StepRun>(new SingleCountRun(g, q, o, ws));
+}
 
 uint64_t match_count_one(gsm_graph &g, const gsm_query &q, const gsm_match_opts &oo, Workspace &ws,
                          const RootSlice &rs) {

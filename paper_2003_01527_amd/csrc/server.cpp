@@ -40,7 +40,7 @@ struct Run {
   std::vector<const gsm_query *> qs;
   std::vector<gsm::RootSlice> slices;
   std::unique_ptr<gsm::Workspace> ws;
-  std::unique_ptr<gsm::BatchRun> br;
+  std::unique_ptr<gsm::StepRun> br;
   uint64_t budget = 0;
   bool solo = false;
   hipEvent_t ev_start = nullptr, ev_end = nullptr;
@@ -140,10 +140,15 @@ struct gsm_server {
         r->ev_start = event();
         r->ev_end = event();
         GSM_HIP(hipEventRecord(r->ev_start, stream));
-        const uint64_t heavy = srv->o.batch_heavy_pairs ? srv->o.batch_heavy_pairs : (uint64_t(1) << 18);
-        const uint64_t evict = (solo || heavy == UINT64_MAX) ? 0 : heavy;
-        r->br.reset(new gsm::BatchRun(*srv->g, r->qs.data(), (int)r->qs.size(), match_opts(r->budget), *r->ws,
-                                      r->slices.data(), evict));
+        if (r->qs.size() == 1) {
+          // one query: the query-uniform kernels are faster than shared launches
+          r->br = gsm::make_single_count_run(*srv->g, *r->qs[0], match_opts(r->budget), *r->ws, r->slices[0]);
+        } else {
+          const uint64_t heavy = srv->o.batch_heavy_pairs ? srv->o.batch_heavy_pairs : (uint64_t(1) << 18);
+          const uint64_t evict = heavy == UINT64_MAX ? 0 : heavy;
+          r->br.reset(new gsm::BatchRun(*srv->g, r->qs.data(), (int)r->qs.size(), match_opts(r->budget), *r->ws,
+                                        r->slices.data(), evict));
+        }
         runs.push_back(std::move(r));
       } catch (const gsm::Error &e) {
         complete(*r, e.status, e.msg, nullptr, nullptr);
