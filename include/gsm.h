@@ -234,6 +234,12 @@ typedef struct gsm_match_opts {
  * neighbours are tested; labelled graphs with the label table only).  Pure
  * pruning: the result is unchanged. */
 #define GSM_MATCH_LOOKAHEAD2 64u
+/* gsm_match_batch: run every level of a group of queries with sizes read back
+ * to the host between levels (the chunked path) instead of device-driven. */
+#define GSM_MATCH_HOST_LEVELS 128u
+/* gsm_match_batch: enqueue the device-driven levels directly instead of
+ * capturing them once in a HIP graph and replaying it. */
+#define GSM_MATCH_NO_GRAPH 256u
 /* Unique-subgraph mode: one embedding per subgraph of the data graph that
  * the query maps onto (the paper's way of producing each node combination
  * once by visiting equivalent query nodes in increasing id order, Sec. 3.3).
@@ -346,7 +352,16 @@ gsm_status gsm_match_min_budget(gsm_graph_t g, gsm_query_t qh, int32_t host_rows
  * like one query).
  * Queries above opts->batch_heavy_pairs first-level pairs run on launches of
  * their own, where a query-uniform kernel is faster.  counts[k] equals
- * gsm_match's count for qs[k].  A root slice in opts (root_qvertex,
+ * gsm_match's count for qs[k].
+ * A group runs device-driven: every level's launches are enqueued at once and
+ * read the level's row count and pair total from device memory, each level
+ * expanded in one chunk at its capacity from the budget, and queries whose
+ * pairs at some level pass batch_heavy_pairs are taken out of the shared
+ * launches on the device (and counted alone afterwards).  The launch sequence
+ * is captured once in a HIP graph and replayed by later calls that ask for
+ * the same work on the same buffers (GSM_MATCH_NO_GRAPH: enqueue directly).
+ * When some level's pairs pass its capacity the group is redone level by
+ * level with sizes read back and chunks (GSM_MATCH_HOST_LEVELS: always).  A root slice in opts (root_qvertex,
  * root_mod, root_rem) applies to every query (root_qvertex must be below
  * every query's size).  No rows or emit callback.
  */

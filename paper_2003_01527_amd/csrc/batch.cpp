@@ -23,6 +23,7 @@ namespace {
 constexpr int kCntRows = 0;
 constexpr int kCntPairs = 16;
 constexpr int kCntProbes = 33;
+constexpr int kCntOverflow = 40;  // device-driven run: a level's pairs passed its capacity
 
 struct BatchMatcher {
   gsm_graph &g;
@@ -309,6 +310,149 @@ struct BatchMatcher {
     sync();
   }
 
+  // ---- device-driven run: every level enqueued at once, its sizes read on
+  // the device (no read-back between levels), each level expanded as one
+  // chunk at its capacity; optionally captured once in a HIP graph and
+  // replayed by later calls that launch the same work.
+
+  // Rows per level the device-driven run provides (level 1: every first
+  // frontier row; deeper: what the level's buffers already hold, at least
+  // kDeviceMinRows, at most the budget's capacity).  A level whose pairs pass
+  // the next one's is flagged; the chunked run that then redoes the group
+  // grows the buffers, so a later run of the same work fits.
+  static constexpr uint64_t kDeviceMinRows = uint64_t(1) << 20;
+  uint64_t dev_cap[kMaxQ] = {0};
+
+  uint64_t held_rows(int i) const {
+    uint64_t r = ws.rows[i].bytes / (4 * (uint64_t)i);
+    r = std::min<uint64_t>(r, ws.W[i].bytes / 4);
+    r = std::min<uint64_t>(r, ws.apos[i].bytes);
+    r = std::min<uint64_t>(r, ws.abase[i].bytes / 8);
+    r = std::min<uint64_t>(r, ws.S[i].bytes / 8 ? ws.S[i].bytes / 8 - 1 : 0);
+    r = std::min<uint64_t>(r, ws.qid[i].bytes / 2);
+    return r;
+  }
+
+  void enqueue_device(hipStream_t st) {
+    uint32_t *overflow = reinterpret_cast<uint32_t *>(dcnt + kCntOverflow);
+    launch_zero_u64(dcnt, 64, st);
+    if (evict_pairs) launch_zero_u64(ws.evicted.as<uint64_t>(), (nq + 1 + 7) / 8, st);
+    launch_compact_first_batch(dg, d_fb, nq, ws.rows[1].as<int32_t>(), ws.qid[1].as<uint16_t>(),
+                               ws.W[1].as<uint32_t>(), ws.abase[1].as<int64_t>(), ws.apos[1].as<uint8_t>(),
+                               dcnt + kCntRows + 1, d_counts, nullptr, st);
+    for (int i = 1; i < maxq; ++i) {
+      if (evict_pairs) {
+        // queries whose pairs at this level pass the threshold leave the
+        // shared launches (decided on the device, kept once decided)
+        launch_zero_u64(ws.qpairs.as<uint64_t>(), nq + 1, st);
+        launch_query_pairs(ws.W[i].as<uint32_t>(), ws.qid[i].as<uint16_t>(), dcnt + kCntRows + i, dev_cap[i],
+                           ws.qpairs.as<uint64_t>(), st);
+        launch_mark_evicted(ws.qpairs.as<uint64_t>(), nq, evict_pairs, ws.evicted.as<uint8_t>(), st);
+        launch_retire_evicted(ws.W[i].as<uint32_t>(), ws.qid[i].as<uint16_t>(), dcnt + kCntRows + i, dev_cap[i],
+                              ws.evicted.as<uint8_t>(), (uint16_t)nq, st);
+      }
+      launch_scan(ws.W[i].as<uint32_t>(), dcnt + kCntRows + i, ws.S[i].as<uint64_t>(), dcnt + kCntPairs + i,
+                  ws.scan_scratch.as<uint64_t>(), st);
+      const bool deepest = (i + 1 >= maxq);
+      ExpandArgs a = level_args(i, 0);
+      a.dev_n_rows = dcnt + kCntRows + i;
+      a.dev_pair_end = dcnt + kCntPairs + i;
+      a.overflow = overflow;
+      a.pair_begin = 0;
+      a.pair_end = deepest ? UINT64_MAX : dev_cap[i + 1];
+      if (!deepest) {
+        launch_zero_u64(dcnt + kCntRows + i + 1, 1, st);
+        a.rows_out = ws.rows[i + 1].as<int32_t>();
+        a.W_out = ws.W[i + 1].as<uint32_t>();
+        a.apos_out = ws.apos[i + 1].as<uint8_t>();
+        a.abase_out = ws.abase[i + 1].as<int64_t>();
+        a.qid_out = ws.qid[i + 1].as<uint16_t>();
+      }
+      a.counter = dcnt + kCntRows + i + 1;
+      launch_expand(a, deepest ? kModeBatchLast : kModeBatch, wg, items, st);
+      ++launches;
+    }
+  }
+
+  // What a captured graph of enqueue_device depends on besides the tables
+  // uploaded before each launch: every pointer and size its launches take.
+  std::string device_key() const {
+    std::string k;
+    auto put = [&](const void *p, size_t n) { k.append(static_cast<const char *>(p), n); };
+    put(&dg, sizeof(dg));
+    put(&nq, sizeof(nq));
+    put(&maxq, sizeof(maxq));
+    put(dev_cap, sizeof(dev_cap));
+    put(&wg, sizeof(wg));
+    put(&items, sizeof(items));
+    put(&evict_pairs, sizeof(evict_pairs));
+    const void *ptrs[] = {d_bl, d_fb, d_counts, dcnt, ws.scan_scratch.ptr, ws.qpairs.ptr, ws.evicted.ptr};
+    put(ptrs, sizeof(ptrs));
+    for (int i = 1; i <= maxq && i < kMaxQ; ++i) {
+      const void *lv[] = {ws.rows[i].ptr, ws.W[i].ptr, ws.apos[i].ptr, ws.abase[i].ptr, ws.S[i].ptr, ws.qid[i].ptr};
+      put(lv, sizeof(lv));
+    }
+    return k;
+  }
+
+  // Runs the group device-driven; false when some level's pairs passed its
+  // capacity (the counts are then not valid: redo with start/step/finish).
+  bool run_device(uint64_t *counts, bool use_graph) {
+    upload_tables();
+    dev_cap[1] = cap[1];
+    for (int i = 2; i < maxq; ++i) dev_cap[i] = std::min(cap[i], std::max(held_rows(i), kDeviceMinRows));
+    for (int i = 1; i < maxq; ++i) reserve_level(i, dev_cap[i]);
+    if (evict_pairs) {
+      ws.qpairs.reserve((nq + 1) * sizeof(uint64_t), s);
+      ws.evicted.reserve(((nq + 1 + 7) / 8) * 8, s);
+      if (evicted.size() != (size_t)nq + 1) evicted.assign(nq + 1, 0);
+    }
+    if (use_graph) {
+      const std::string key = device_key();
+      auto hit = std::find_if(ws.graphs.begin(), ws.graphs.end(),
+                              [&](const std::pair<std::string, hipGraphExec_t> &e) { return e.first == key; });
+      hipGraphExec_t exec = nullptr;
+      if (hit != ws.graphs.end()) {
+        exec = hit->second;
+        std::rotate(hit, hit + 1, ws.graphs.end());  // most recent last
+        launches += maxq - 1;
+      } else {
+        if (!ws.capture_stream) GSM_HIP(hipStreamCreateWithFlags(&ws.capture_stream, hipStreamNonBlocking));
+        GSM_HIP(hipStreamBeginCapture(ws.capture_stream, hipStreamCaptureModeThreadLocal));
+        hipGraph_t graph = nullptr;
+        try {
+          enqueue_device(ws.capture_stream);
+        } catch (...) {
+          (void)hipStreamEndCapture(ws.capture_stream, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          throw;
+        }
+        GSM_HIP(hipStreamEndCapture(ws.capture_stream, &graph));
+        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) throw Error{GSM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+        if (ws.graphs.size() >= Workspace::kMaxGraphs) {
+          (void)hipGraphExecDestroy(ws.graphs.front().second);
+          ws.graphs.erase(ws.graphs.begin());
+        }
+        ws.graphs.emplace_back(key, exec);
+      }
+      GSM_HIP(hipGraphLaunch(exec, s));
+    } else {
+      enqueue_device(s);
+    }
+    GSM_HIP(hipMemcpyAsync(ws.h_counters, dcnt, 64 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    GSM_HIP(hipMemcpyAsync(counts, d_counts, nq * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    if (evict_pairs) GSM_HIP(hipMemcpyAsync(evicted.data(), ws.evicted.ptr, nq + 1, hipMemcpyDeviceToHost, s));
+    sync();
+    if (ws.h_counters[kCntOverflow] & 0xffffffffull) return false;
+    for (int i = 1; i < maxq; ++i) {
+      level_rows[i] += ws.h_counters[kCntRows + i];
+      level_pairs[i] += ws.h_counters[kCntPairs + i];
+    }
+    return true;
+  }
+
   // First-level (row, neighbour) pairs of every query, from the first-frontier
   // kernel in estimate mode (nothing is written but the totals).
   std::vector<uint64_t> first_level_pairs() {
@@ -368,6 +512,7 @@ void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_
                     const RootSlice *slices) {
     auto slice_of = [&](int k) { return slices ? slices[k] : RootSlice{}; };
     const hipStream_t stream = (hipStream_t)o.hip_stream;
+    const uint32_t flags = o.struct_size >= offsetof(gsm_match_opts, flags) + sizeof(uint32_t) ? o.flags : 0u;
     auto configure = [&](BatchMatcher &m) {
       m.rounds = o.filter_rounds;
       m.use_deg = o.use_degree;
@@ -409,7 +554,23 @@ void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_
       configure(m);
       m.evict_pairs = heavy_pairs_opt == UINT64_MAX ? 0 : heavy_pairs_opt;
       m.plan_capacity();
-      m.run(c.data());
+      const bool device_ok = !(flags & GSM_MATCH_HOST_LEVELS);
+      if (!device_ok || !m.run_device(c.data(), !(flags & GSM_MATCH_NO_GRAPH))) {
+        // a level did not fit its capacity in one chunk: level by level,
+        // chunked, sizes read back
+        BatchMatcher again(g, sub.data(), (int)sub.size(), ws, stream, sub_sl.data());
+        configure(again);
+        again.evict_pairs = m.evict_pairs;
+        again.plan_capacity();
+        again.run(c.data());
+        again.launches += m.launches;
+        std::swap(m.evicted, again.evicted);
+        for (int i = 0; i < kMaxQ; ++i) {
+          m.level_pairs[i] = again.level_pairs[i];
+          m.level_rows[i] = again.level_rows[i];
+        }
+        m.launches = again.launches;
+      }
       launches += m.launches;
       if (st)
         for (int i = 0; i < kMaxQ; ++i) {

@@ -52,7 +52,20 @@ __global__ __launch_bounds__(kAuxWG) void k_retire_evicted(uint32_t *W, uint16_t
     }
 }
 
+__global__ __launch_bounds__(kAuxWG) void k_mark_evicted(const uint64_t *qpairs, int nq, uint64_t threshold,
+                                                         uint8_t *evicted) {
+  for (int k = blockIdx.x * kAuxWG + threadIdx.x; k < nq; k += gridDim.x * kAuxWG)
+    if (qpairs[k] > threshold) evicted[k] = 1;
+}
+
 }  // namespace
+
+void launch_mark_evicted(const uint64_t *qpairs, int nq, uint64_t threshold, uint8_t *evicted, hipStream_t s) {
+  if (nq <= 0) return;
+  const unsigned grid = (unsigned)std::min<int>((nq + kAuxWG - 1) / kAuxWG, 1024);
+  hipLaunchKernelGGL(k_mark_evicted, dim3(grid), dim3(kAuxWG), 0, s, qpairs, nq, threshold, evicted);
+  GSM_HIP(hipGetLastError());
+}
 
 void launch_query_pairs(const uint32_t *W, const uint16_t *qid, const uint64_t *n_dev, uint64_t rows_hint,
                         uint64_t *qpairs, hipStream_t s) {

@@ -144,6 +144,8 @@ Workspace::Workspace(void *base, size_t bytes) {
 }
 
 Workspace::~Workspace() {
+  for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  if (capture_stream) (void)hipStreamDestroy(capture_stream);
   if (h_counters && h_counters != h_local) (void)hipHostFree(h_counters);
   for (auto &e : events) (void)hipEventDestroy(e);
 }

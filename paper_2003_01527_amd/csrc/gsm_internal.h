@@ -299,6 +299,12 @@ struct ExpandArgs {
   // words per row of i ids): the input rows (pack_in, then they are always
   // staged in LDS) and the next level's rows (pack_out, kModeNext)
   int32_t pack_bits, pack_in, pack_out;
+  // device-driven launch (dev_pair_end != null): the row count and the pair
+  // total are read from *dev_n_rows and *dev_pair_end; pair_end is then the
+  // capacity bound, and a total above it sets *overflow
+  const uint64_t *dev_n_rows;
+  const uint64_t *dev_pair_end;
+  uint32_t *overflow;
   int32_t staged;        // output rows pass through LDS (dynamic shared memory)
   int32_t stage_in;      // the tile's input rows are copied to LDS
   int32_t stage_out_ok;  // the caller allows output staging
@@ -317,6 +323,8 @@ void launch_query_pairs(const uint32_t *W, const uint16_t *qid, const uint64_t *
                         uint64_t *qpairs, hipStream_t s);
 void launch_retire_evicted(uint32_t *W, uint16_t *qid, const uint64_t *n_dev, uint64_t rows_hint,
                            const uint8_t *evicted, uint16_t retired, hipStream_t s);
+// evicted[k] = 1 for every query k < nq with qpairs[k] > threshold (kept once set).
+void launch_mark_evicted(const uint64_t *qpairs, int nq, uint64_t threshold, uint8_t *evicted, hipStream_t s);
 
 // First frontier of every query: rows tagged with the query id; queries with a
 // single vertex are counted into counts[k] directly.
@@ -415,6 +423,13 @@ struct Workspace {
   char *fixed_base = nullptr;
   size_t fixed_bytes = 0;
   uint64_t h_local[64];
+  // batched groups run device-driven: the captured launch sequences of the
+  // most recent groups, replayed while the same work is asked for again
+  // (key: every pointer and size the launches take; most recent last), and
+  // the stream they are captured on
+  std::vector<std::pair<std::string, hipGraphExec_t>> graphs;
+  hipStream_t capture_stream = nullptr;
+  static constexpr size_t kMaxGraphs = 16;
   Workspace();
   Workspace(void *base, size_t bytes);  // fixed
   ~Workspace();

@@ -511,7 +511,18 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
   const bool stage_in = a.stage_in != 0;
   int32_t *s_in = dyn;
   int32_t *s_out = dyn + (stage_in ? TILE * i : 0);
-  const uint64_t npairs = a.pair_end - a.pair_begin;
+  // rows and pair range: from the arguments, or (device-driven launches) the
+  // level's row count and scan total as the previous kernels left them in
+  // device memory, the range then clamped to the capacity the host gave; a
+  // total above it is flagged, and the host redoes the work in chunks
+  uint64_t n_rows = a.n_rows, pair_end = a.pair_end;
+  if (a.dev_pair_end) {
+    n_rows = *a.dev_n_rows;
+    const uint64_t total = *a.dev_pair_end;
+    pair_end = min(a.pair_end, total);
+    if (total > a.pair_end && blockIdx.x == 0 && threadIdx.x == 0) *a.overflow = 1;
+  }
+  const uint64_t npairs = pair_end > a.pair_begin ? pair_end - a.pair_begin : 0;
   const uint64_t ntiles = (npairs + TILE - 1) / TILE;
   const uint32_t G = gridDim.x, b = blockIdx.x;
   // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
@@ -525,11 +536,11 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
 
   for (uint64_t tile = lb; tile < ntiles; tile += G) {
     const uint64_t t0 = a.pair_begin + tile * TILE;
-    const uint32_t len = (uint32_t)min((uint64_t)TILE, a.pair_end - t0);
+    const uint32_t len = (uint32_t)min((uint64_t)TILE, pair_end - t0);
     if (wid == 0) {
       // 64-way search by the first wave: S[lo] <= t0 < S[hi]; every round
       // shrinks the interval 64-fold (5 dependent loads for 10^8 rows).
-      uint64_t lo = 0, hi = a.n_rows;
+      uint64_t lo = 0, hi = n_rows;
       while (hi - lo > 1) {
         const uint64_t step = (hi - lo + kWave - 1) / kWave;
         const uint64_t idx = lo + (uint64_t)lane * step;
@@ -551,7 +562,7 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
         rel = 0;  // the first row may start before the tile: its lead is s_lead
         s_lead = (uint32_t)(t0 - a.S[r0]);
       } else {
-        const uint64_t v = (r <= a.n_rows) ? a.S[r] : ~0ull;
+        const uint64_t v = (r <= n_rows) ? a.S[r] : ~0ull;
         rel = (v - t0 > (uint64_t)TILE) ? (uint32_t)TILE + 1 : (uint32_t)(v - t0);
       }
       sS[k] = rel;
@@ -983,7 +994,8 @@ constexpr size_t kMaxStageBytes = kExpandStageBytes;
 template <int WG, int ITEMS>
 void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
   constexpr uint64_t TILE = (uint64_t)WG * ITEMS;
-  const uint64_t ntiles = (a.pair_end - a.pair_begin + TILE - 1) / TILE;
+  const uint64_t span = a.pair_end - a.pair_begin;  // an upper bound when the range is read on the device
+  const uint64_t ntiles = span / TILE + (span % TILE != 0);
   if (ntiles == 0) return;
   // persistent-style grid: a few workgroups per CU loop over the tiles, so
   // per-workgroup reductions end in few atomics

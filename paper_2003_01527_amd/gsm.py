@@ -234,13 +234,16 @@ FLAG_UNIQUE = 8
 FLAG_INDUCED = 16
 FLAG_PACK_FRONTIER = 32
 FLAG_LOOKAHEAD2 = 64
+FLAG_HOST_LEVELS = 128
+FLAG_NO_GRAPH = 256
 
 
 def make_opts(budget: int = 0, filter_rounds: int = 1, use_degree: bool = True, use_ne: bool = True,
               stream=None, root=None, tile_items: int = 0, wg_size: int = 0, profile: bool = False,
               stats: Optional[Stats] = None, stage_output: bool = True, sort_rows: bool = False,
               lookahead: bool = False, unique: bool = False, induced: bool = False, batch_heavy_pairs: int = 0,
-              pack_frontier: bool = False, lookahead2: bool = False) -> MatchOpts:
+              pack_frontier: bool = False, lookahead2: bool = False, host_levels: bool = False,
+              no_graph: bool = False) -> MatchOpts:
     o = MatchOpts()
     _load().gsm_match_opts_init(ctypes.byref(o))
     o.memory_budget_bytes = int(budget)
@@ -257,7 +260,8 @@ def make_opts(budget: int = 0, filter_rounds: int = 1, use_degree: bool = True, 
     o.flags = ((0 if stage_output else FLAG_NO_OUTPUT_STAGING) | (FLAG_SORT_ROWS if sort_rows else 0)
                | (FLAG_LOOKAHEAD if lookahead else 0) | (FLAG_UNIQUE if unique else 0)
                | (FLAG_INDUCED if induced else 0) | (FLAG_PACK_FRONTIER if pack_frontier else 0)
-               | (FLAG_LOOKAHEAD2 if lookahead2 else 0))
+               | (FLAG_LOOKAHEAD2 if lookahead2 else 0) | (FLAG_HOST_LEVELS if host_levels else 0)
+               | (FLAG_NO_GRAPH if no_graph else 0))
     o.batch_heavy_pairs = int(batch_heavy_pairs)
     if stats is not None:
         stats.struct_size = ctypes.sizeof(Stats)

@@ -102,6 +102,8 @@ def test_binding_flags_match_header():
     assert defs["GSM_MATCH_INDUCED"] == gsm.FLAG_INDUCED
     assert defs["GSM_MATCH_PACK_FRONTIER"] == gsm.FLAG_PACK_FRONTIER
     assert defs["GSM_MATCH_LOOKAHEAD2"] == gsm.FLAG_LOOKAHEAD2
+    assert defs["GSM_MATCH_HOST_LEVELS"] == gsm.FLAG_HOST_LEVELS
+    assert defs["GSM_MATCH_NO_GRAPH"] == gsm.FLAG_NO_GRAPH
     assert defs["GSM_MAX_QUERY_VERTICES"] == 16
     flags = gsm.make_opts(sort_rows=True, lookahead=True, unique=True, induced=True, stage_output=False).flags
     assert flags == (gsm.FLAG_SORT_ROWS | gsm.FLAG_LOOKAHEAD | gsm.FLAG_UNIQUE | gsm.FLAG_INDUCED

@@ -100,3 +100,52 @@ def test_large_graph_slices_equal_oracle():
         assert c == int(cnt), (name, rem, c, cnt)
         nonzero += c > 0
     assert nonzero >= len(rows) // 2
+
+
+NEVER = (1 << 64) - 1
+
+
+def test_batch_device_driven_paths_equal_oracle(batch_workload):
+    # the same counts with levels read back between launches, enqueued
+    # device-driven without a graph, and replayed from a captured graph
+    w, G, Qs, expect = batch_workload
+    for kw in (dict(host_levels=True), dict(no_graph=True), dict()):
+        got = gsm.match_batch(G, Qs, root=BATCH_SLICE, batch_heavy_pairs=NEVER, **kw)
+        np.testing.assert_array_equal(got, expect)
+
+
+def test_batch_graph_replays_with_eager_work_between(batch_workload):
+    """The captured graph is replayed by later identical calls; eager library
+    and torch work and synchronisations run between the replays, and every
+    replay's counts equal the oracle's."""
+    import torch
+    w, G, Qs, expect = batch_workload
+    sub = list(range(0, len(Qs), 3))
+    Qsub = [Qs[k] for k in sub]
+    other = gsm.Query.from_workload(w.queries[1])
+    c_other = gsm.match(G, other, root=BATCH_SLICE)[0]
+    x = torch.arange(1 << 20, device="cuda:0", dtype=torch.int64)
+    for rep in range(5):
+        got = gsm.match_batch(G, Qsub, root=BATCH_SLICE, batch_heavy_pairs=NEVER)
+        np.testing.assert_array_equal(got, expect[sub]), rep
+        # eager work between replays: a single-query match, torch kernels, a sync
+        assert gsm.match(G, other, root=BATCH_SLICE)[0] == c_other
+        assert int((x * 3).sum().item()) == 3 * ((1 << 20) - 1) * (1 << 20) // 2
+        torch.cuda.synchronize()
+    # a different batch in between, then the first again (captured anew)
+    got2 = gsm.match_batch(G, Qs[:50], root=BATCH_SLICE, batch_heavy_pairs=NEVER)
+    np.testing.assert_array_equal(got2, expect[:50])
+    got = gsm.match_batch(G, Qsub, root=BATCH_SLICE, batch_heavy_pairs=NEVER)
+    np.testing.assert_array_equal(got, expect[sub])
+
+
+def test_batch_device_driven_eviction_and_overflow(batch_workload):
+    # eviction decided on the device, and a budget so small that some level
+    # passes its capacity (the group is redone level by level)
+    w, G, Qs, expect = batch_workload
+    for hp in (1 << 12, 1 << 16):
+        got = gsm.match_batch(G, Qs, root=BATCH_SLICE, batch_heavy_pairs=hp)
+        np.testing.assert_array_equal(got, expect)
+    sub = list(range(0, len(Qs), 5))
+    got = gsm.match_batch(G, [Qs[k] for k in sub], root=BATCH_SLICE, batch_heavy_pairs=NEVER, budget=64 << 20)
+    np.testing.assert_array_equal(got, expect[sub])
