@@ -467,7 +467,8 @@ def bench_batch(args):
     stream = torch.cuda.current_stream().cuda_stream
     best = autotune.tune_batch(G, Qs, w.queries, budget, cache_path=args.tune_cache, log=log)
     log("autotuned: %s" % best)
-    kw = dict(budget=budget, stream=stream, wg_size=best["wg_size"], tile_items=best["tile_items"])
+    kw = dict(budget=best.get("budget", budget), stream=stream, wg_size=best["wg_size"],
+              tile_items=best["tile_items"], stage_bytes=best.get("stage_bytes", 0))
 
     def per_launch():
         return np.array([gsm.match(G, Q, **kw)[0] for Q in Qs], dtype=np.uint64)

@@ -211,6 +211,9 @@ typedef struct gsm_match_opts {
   uint64_t batch_heavy_pairs;   /* gsm_match_batch: a query whose first level has more
                                    (row, neighbour) pairs runs on launches of its own
                                    (0 = 2^18; UINT64_MAX = never) */
+  uint32_t stage_bytes;         /* LDS bytes an expansion launch may use to stage its tile's
+                                   input and output rows (0 = 48 KiB; at most 64 KiB): a launch
+                                   shape, results unchanged */
 } gsm_match_opts;
 
 /* Write output rows straight from registers instead of staging them in LDS. */

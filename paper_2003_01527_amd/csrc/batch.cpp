@@ -31,6 +31,7 @@ struct BatchMatcher {
   Workspace &ws;
   hipStream_t s;
   int rounds, use_deg, use_ne, wg, items;
+  uint32_t stage_bytes = 0;
   uint64_t budget;
   int nq = 0, maxq = 0;
   std::vector<Plan> plans;
@@ -243,6 +244,7 @@ struct BatchMatcher {
     a.counts = d_counts;
     a.probes = dcnt + kCntProbes;
     a.stage_out_ok = 1;
+    a.stage_limit = stage_bytes;
     return a;
   }
 
@@ -386,6 +388,7 @@ struct BatchMatcher {
     put(&wg, sizeof(wg));
     put(&items, sizeof(items));
     put(&evict_pairs, sizeof(evict_pairs));
+    put(&stage_bytes, sizeof(stage_bytes));
     const void *ptrs[] = {d_bl, d_fb, d_counts, dcnt, ws.scan_scratch.ptr, ws.qpairs.ptr, ws.evicted.ptr};
     put(ptrs, sizeof(ptrs));
     for (int i = 1; i <= maxq && i < kMaxQ; ++i) {
@@ -492,6 +495,7 @@ BatchRun::BatchRun(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_m
   m.wg = o.wg_size ? o.wg_size : 512;
   m.items = o.tile_items ? o.tile_items : 4;
   m.budget = o.memory_budget_bytes ? o.memory_budget_bytes : (uint64_t(4) << 30);
+  if (o.struct_size >= offsetof(gsm_match_opts, stage_bytes) + sizeof(uint32_t)) m.stage_bytes = o.stage_bytes;
   m.evict_pairs = evict_pairs;
   m.plan_capacity();
   m.start();
@@ -520,6 +524,7 @@ void match_batch_on(gsm_graph &g, const gsm_query *const *qs, int nq, const gsm_
       m.wg = o.wg_size ? o.wg_size : 512;
       m.items = o.tile_items ? o.tile_items : 4;
       m.budget = o.memory_budget_bytes ? o.memory_budget_bytes : (uint64_t(4) << 30);
+      if (o.struct_size >= offsetof(gsm_match_opts, stage_bytes) + sizeof(uint32_t)) m.stage_bytes = o.stage_bytes;
     };
     const uint64_t heavy_pairs_opt = o.batch_heavy_pairs ? o.batch_heavy_pairs : (uint64_t(1) << 18);
     // split: heavy queries on launches of their own, the rest shared
@@ -639,6 +644,9 @@ extern "C" gsm_status gsm_match_batch(gsm_graph_t g, int32_t nq, const gsm_query
       slices.assign(nq, gsm::RootSlice{o.root_qvertex, o.root_mod, o.root_rem});
     }
     if (o.filter_rounds < 0 || o.filter_rounds > 64) throw Error{GSM_E_INVALID_ARG, "filter_rounds out of [0, 64]"};
+    if (o.struct_size >= offsetof(gsm_match_opts, stage_bytes) + sizeof(uint32_t) &&
+        o.stage_bytes > gsm::kExpandStageMax)
+      throw Error{GSM_E_INVALID_ARG, "stage_bytes above 64 KiB"};
     std::lock_guard<std::mutex> lk(g->mu);
     if (!g->ws) g->ws = new gsm::Workspace();
     uint64_t launches = 0;

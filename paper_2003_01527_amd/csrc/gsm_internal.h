@@ -305,6 +305,7 @@ struct ExpandArgs {
   const uint64_t *dev_n_rows;
   const uint64_t *dev_pair_end;
   uint32_t *overflow;
+  uint32_t stage_limit;  // LDS bytes for staging rows (0 = kExpandStageBytes)
   int32_t staged;        // output rows pass through LDS (dynamic shared memory)
   int32_t stage_in;      // the tile's input rows are copied to LDS
   int32_t stage_out_ok;  // the caller allows output staging
@@ -312,8 +313,10 @@ struct ExpandArgs {
 };
 
 void launch_expand(const ExpandArgs &a, int mode, int wg, int items, hipStream_t s);
-// Most LDS a launch uses to stage its tile's input and output rows.
+// Most LDS a launch uses to stage its tile's input and output rows, by
+// default and at most.
 constexpr size_t kExpandStageBytes = 48 * 1024;
+constexpr size_t kExpandStageMax = 64 * 1024;
 
 // Batched helpers: qpairs[q] += W[r] over the *n_dev rows r of query qid[r];
 // rows whose query is marked in evicted get W = 1 and qid = retired (a query

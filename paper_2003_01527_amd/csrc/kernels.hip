@@ -1006,12 +1006,13 @@ void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
   const int width = (mode == kModeNext || mode == kModeBatch) ? a.L.i + 1 : a.L.q;
   const size_t in_bytes = TILE * (size_t)a.L.i * sizeof(int32_t);
   const size_t out_bytes = TILE * (size_t)width * sizeof(int32_t);
-  a.stage_in = (in_bytes <= kMaxStageBytes) ? 1 : 0;
+  const size_t stage_max = a.stage_limit ? a.stage_limit : kMaxStageBytes;
+  a.stage_in = (in_bytes <= stage_max) ? 1 : 0;
   if (a.pack_in && !a.stage_in) throw Error{GSM_E_DEVICE, "packed frontier rows need staging"};
   if ((a.pack_in || a.pack_out) && (mode == kModeBatch || mode == kModeBatchLast))
     throw Error{GSM_E_DEVICE, "packed frontier rows in a batched launch"};
   a.staged = (a.stage_out_ok && !(mode == kModeNext && a.pack_out) && mode != kModeCount &&
-              mode != kModeBatchLast && (a.stage_in ? in_bytes : 0) + out_bytes <= kMaxStageBytes)
+              mode != kModeBatchLast && (a.stage_in ? in_bytes : 0) + out_bytes <= stage_max)
                  ? 1
                  : 0;
   const size_t smem = (a.stage_in ? in_bytes : 0) + (a.staged ? out_bytes : 0);

@@ -38,6 +38,7 @@ struct Options {
   bool unique = false;
   bool induced = false;
   bool pack = false;
+  uint32_t stage_bytes = kExpandStageBytes;
 };
 
 Options read_opts(const gsm_match_opts *o, int q) {
@@ -67,6 +68,10 @@ Options read_opts(const gsm_match_opts *o, int q) {
     r.unique = (o->flags & GSM_MATCH_UNIQUE) != 0;
     r.induced = (o->flags & GSM_MATCH_INDUCED) != 0;
     r.pack = (o->flags & GSM_MATCH_PACK_FRONTIER) != 0;
+  }
+  if (o->struct_size >= offsetof(gsm_match_opts, stage_bytes) + sizeof(uint32_t) && o->stage_bytes) {
+    if (o->stage_bytes > kExpandStageMax) throw Error{GSM_E_INVALID_ARG, "stage_bytes above 64 KiB"};
+    r.stage_bytes = o->stage_bytes;
   }
   if (r.rounds < 0 || r.rounds > 64) throw Error{GSM_E_INVALID_ARG, "filter_rounds out of [0, 64]"};
   if (r.root_q >= q) throw Error{GSM_E_INVALID_ARG, "root_qvertex >= q"};
@@ -134,7 +139,7 @@ struct Matcher {
       // level i is packed when that saves bytes and its consumer can stage
       // its rows in LDS (the decoder runs there)
       for (int i = 2; i < p.q; ++i)
-        packed[i] = (i * pack_bits + 31) / 32 < i && (uint64_t)o.wg * o.items * i * 4 <= kExpandStageBytes;
+        packed[i] = (i * pack_bits + 31) / 32 < i && (uint64_t)o.wg * o.items * i * 4 <= o.stage_bytes;
     }
   }
 
@@ -207,6 +212,7 @@ struct Matcher {
   void expand(ExpandArgs &a, int mode) {
     a.probes = dcnt + kCntProbes;
     a.stage_out_ok = o.stage_out;
+    a.stage_limit = o.stage_bytes;
     if (o.profile) {
       auto pr = next_events();
       GSM_HIP(hipEventRecord(pr.first, s));

@@ -71,7 +71,8 @@ class MatchOpts(ctypes.Structure):
                 ("emit", EMIT_FN), ("emit_ctx", ctypes.c_void_p),
                 ("stats", ctypes.POINTER(Stats)), ("tile_items", ctypes.c_int32),
                 ("wg_size", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("batch_heavy_pairs", ctypes.c_uint64)]
+                ("flags", ctypes.c_uint32), ("batch_heavy_pairs", ctypes.c_uint64),
+                ("stage_bytes", ctypes.c_uint32)]
 
 
 def library_path() -> str:
@@ -243,7 +244,7 @@ def make_opts(budget: int = 0, filter_rounds: int = 1, use_degree: bool = True, 
               stats: Optional[Stats] = None, stage_output: bool = True, sort_rows: bool = False,
               lookahead: bool = False, unique: bool = False, induced: bool = False, batch_heavy_pairs: int = 0,
               pack_frontier: bool = False, lookahead2: bool = False, host_levels: bool = False,
-              no_graph: bool = False) -> MatchOpts:
+              no_graph: bool = False, stage_bytes: int = 0) -> MatchOpts:
     o = MatchOpts()
     _load().gsm_match_opts_init(ctypes.byref(o))
     o.memory_budget_bytes = int(budget)
@@ -263,6 +264,7 @@ def make_opts(budget: int = 0, filter_rounds: int = 1, use_degree: bool = True, 
                | (FLAG_LOOKAHEAD2 if lookahead2 else 0) | (FLAG_HOST_LEVELS if host_levels else 0)
                | (FLAG_NO_GRAPH if no_graph else 0))
     o.batch_heavy_pairs = int(batch_heavy_pairs)
+    o.stage_bytes = int(stage_bytes)
     if stats is not None:
         stats.struct_size = ctypes.sizeof(Stats)
         o.stats = ctypes.pointer(stats)

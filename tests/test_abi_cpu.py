@@ -46,7 +46,7 @@ def test_status_strings():
 
 def test_struct_sizes_match_header():
     # gsm_match_opts: u32 + pad, u64, 4 x i32, ptr, i32, 2 x u32, 3 ptrs, 3 x i32 (+pad)
-    assert ctypes.sizeof(gsm.MatchOpts) == 104
+    assert ctypes.sizeof(gsm.MatchOpts) == 112
     assert ctypes.sizeof(gsm.Stats) == 8 + 8 + 3 * 16 * 8 + 4 * 8 + 2 * 8 + 8
     o = gsm.make_opts()
     assert o.struct_size == ctypes.sizeof(gsm.MatchOpts)
