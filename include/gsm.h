@@ -69,6 +69,7 @@ typedef enum gsm_status {
 #define GSM_GRAPH_VALIDATE 1u    /* check the CSR (see gsm_graph_create) */
 #define GSM_GRAPH_DEVICE_PTRS 2u /* row_ptr, col, labels are device pointers */
 #define GSM_GRAPH_STRIP 4u       /* make the adjacency simple and undirected first */
+#define GSM_GRAPH_NO_HUB_BITMAPS 8u /* no adjacency bitmaps for high-degree vertices */
 
 /*
  * Uploads a data graph.  The graph must be simple and undirected: each edge
@@ -86,7 +87,11 @@ typedef enum gsm_status {
  *            in [0, n): self-loops are dropped, each entry v->w also adds
  *            w->v, rows are sorted and duplicates removed, on the host, before
  *            the upload (GSM_E_BAD_GRAPH only for bad offsets or ids).
- * Also computes per-vertex degree and neighbourhood encoding on the device.
+ * Also computes per-vertex degree and neighbourhood encoding on the device,
+ * and, unless GSM_GRAPH_NO_HUB_BITMAPS, an adjacency bitmap (n bits) for each
+ * vertex of degree >= 2048, highest degree first, while they fit 512 MiB:
+ * an edge check against such a vertex is then one load instead of a search
+ * of its sorted list (results are the same).
  */
 gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col,
                             const int32_t *labels, uint32_t flags, gsm_graph_t *out);

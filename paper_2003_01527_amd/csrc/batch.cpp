@@ -58,8 +58,7 @@ struct BatchMatcher {
       : g(g_), qs(q_, q_ + nq_), ws(ws_), s(s_), nq(nq_) {
     slices.assign(nq, RootSlice{});
     if (sl) slices.assign(sl, sl + nq);
-    dg = DeviceGraph{g.rp,  g.col,  g.lab, g.deg, g.ne0, g.dne, g.col_lab ? g.col_lab : g.col,
-                     g.loff, g.loff_stride, g.n, g.elab, g.elab_lab ? g.elab_lab : g.elab};
+    dg = device_graph(g);
     dcnt = ws.counters.as<uint64_t>();
     for (auto *q : qs) {
       plans.push_back(make_plan(g, *q));

@@ -466,6 +466,43 @@ gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t 
       gsm::device_alloc((void **)&g->heavy, heavy.size() * sizeof(int32_t));
       GSM_HIP(hipMemcpy(g->heavy, heavy.data(), heavy.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
+    if (!(flags & GSM_GRAPH_NO_HUB_BITMAPS) && n > 0) {
+      // adjacency bitmaps of the highest-degree vertices, while they fit
+      const uint64_t words = ((uint64_t)n + 31) / 32;
+      const uint64_t fit = gsm::kHubBitmapBytes / (words * 4);
+      std::vector<int32_t> hubs;
+      for (int64_t v = 0; v < n; ++v)
+        if (h_rp[v + 1] - h_rp[v] >= gsm::kHubMinDegree) hubs.push_back((int32_t)v);
+      std::stable_sort(hubs.begin(), hubs.end(), [&](int32_t a, int32_t b) {
+        return h_rp[a + 1] - h_rp[a] > h_rp[b + 1] - h_rp[b];
+      });
+      if (hubs.size() > fit) hubs.resize(fit);
+      if (!hubs.empty()) {
+        std::vector<int32_t> slot((size_t)n, -1);
+        for (size_t k = 0; k < hubs.size(); ++k) slot[hubs[k]] = (int32_t)k;
+        gsm::device_alloc((void **)&g->hub_slot, (size_t)n * sizeof(int32_t));
+        GSM_HIP(hipMemcpy(g->hub_slot, slot.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice));
+        gsm::device_alloc((void **)&g->hub_bits, hubs.size() * words * 4);
+        GSM_HIP(hipMemset(g->hub_bits, 0, hubs.size() * words * 4));
+        int32_t *d_hubs = nullptr;
+        gsm::device_alloc((void **)&d_hubs, hubs.size() * sizeof(int32_t));
+        hipError_t e = hipMemcpy(d_hubs, hubs.data(), hubs.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        g->hub_words = words;
+        g->nhubs = (int64_t)hubs.size();
+        if (e == hipSuccess) {
+          try {
+            gsm::launch_build_hub_bitmaps(*g, d_hubs, g->nhubs, nullptr);
+          } catch (...) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(d_hubs);
+            throw;
+          }
+          e = hipDeviceSynchronize();
+        }
+        (void)hipFree(d_hubs);
+        if (e != hipSuccess) throw Error{GSM_E_DEVICE, std::string("hub bitmaps: ") + hipGetErrorString(e)};
+      }
+    }
     GSM_HIP(hipDeviceSynchronize());
   } catch (...) {
     gsm_graph_destroy(g);
@@ -487,6 +524,8 @@ void gsm_graph_destroy(gsm_graph_t g) {
   (void)hipFree(g->dne);
   (void)hipFree(g->ne0);
   (void)hipFree(g->heavy);
+  (void)hipFree(g->hub_slot);
+  (void)hipFree(g->hub_bits);
   (void)hipFree(g->col_lab);
   (void)hipFree(g->loff);
   (void)hipFree(g->elab);

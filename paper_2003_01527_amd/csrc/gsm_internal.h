@@ -89,6 +89,13 @@ struct gsm_graph {
   uint2 *dne = nullptr;      // n: (degree, NE saturated to 32 bits): one load per inline test
   int32_t *heavy = nullptr;  // vertices with degree > kHeavyDegree
   int64_t nheavy = 0;
+  // adjacency bitmaps of the highest-degree vertices (membership in one load):
+  // hub_slot[v] = bitmap index of v or -1; bitmap s is hub_words 32-bit words
+  // at hub_bits + s * hub_words, bit w set when w is a neighbour
+  int32_t *hub_slot = nullptr;
+  uint32_t *hub_bits = nullptr;
+  uint64_t hub_words = 0;
+  int64_t nhubs = 0;
   // label-grouped adjacency (labelled graphs with at most kMaxTableLabels labels):
   // row v of col_lab holds v's neighbours sorted by (label, id), and
   // loff[v * loff_stride + l] is where label l starts inside that row.
@@ -121,6 +128,10 @@ struct gsm_query {
 namespace gsm {
 
 constexpr int64_t kHeavyDegree = 2048;
+// Vertices of at least this degree get an adjacency bitmap, highest degree
+// first, while the bitmaps fit kHubBitmapBytes.
+constexpr int64_t kHubMinDegree = 2048;
+constexpr uint64_t kHubBitmapBytes = uint64_t(512) << 20;
 constexpr int32_t kMaxTableLabels = 64;
 
 // ------------------------------------------------------------------- plan --
@@ -217,6 +228,9 @@ struct DeviceGraph {
   int64_t n;
   const int32_t *elab;         // edge label per col entry, or null (every edge has label 0)
   const int32_t *elab_gather;  // edge label per gather entry, or null
+  const int32_t *hub_slot;     // bitmap index per vertex (-1: none), or null
+  const uint32_t *hub_bits;
+  uint64_t hub_words;
 };
 
 // Each launcher enqueues on `s` and returns immediately.
@@ -232,6 +246,11 @@ void launch_compact_first(const DeviceGraph &g, const uint16_t *cmask, uint32_t 
                           uint8_t *apos, uint64_t *counter, int32_t *emit_rows, uint64_t emit_cap,
                           hipStream_t s);
 void build_label_table(gsm_graph &g, const int64_t *h_rp, const int32_t *h_col, const int32_t *h_lab);
+// Adjacency bitmaps of the listed vertices (hub_slot, hub_bits already
+// allocated and hub_bits zeroed): bitmap s gets the neighbours of hubs[s].
+void launch_build_hub_bitmaps(const gsm_graph &g, const int32_t *hubs, int64_t nhubs, hipStream_t s);
+// The device view of a graph.
+DeviceGraph device_graph(const gsm_graph &g);
 // S[0..N] = exclusive scan of W[0..N-1]; N read from device *n_dev; scratch >= scan_scratch_bytes()
 size_t scan_scratch_elems();
 // p[0..count) = 0 with a kernel (no memset node, so a captured stream replays it correctly)

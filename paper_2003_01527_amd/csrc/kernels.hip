@@ -91,6 +91,9 @@ __device__ __forceinline__ bool has_edge(const DeviceGraph &g, int32_t x, int32_
   const int64_t b = g.rp[x];
   const uint32_t n = (uint32_t)(g.rp[x + 1] - b);
   probes += search_steps(n);
+  // only lists of at least kHubMinDegree entries can have a bitmap
+  const int32_t hs = (g.hub_slot && n >= (uint32_t)kHubMinDegree) ? g.hub_slot[x] : -1;
+  if (hs >= 0) return (g.hub_bits[(uint64_t)hs * g.hub_words + ((uint32_t)w >> 5)] >> (w & 31)) & 1u;
   return find_sorted(g.col + b, n, w) >= 0;
 }
 
@@ -124,6 +127,19 @@ __global__ void k_graph_stats(const int64_t *rp, const int32_t *col, const int32
       if (ne0) ne0[v] = s;
       const uint64_t ne = lab ? s : (uint64_t)(e - b);
       dne[v] = make_uint2((uint32_t)(e - b), ne > 0xffffffffull ? 0xffffffffu : (uint32_t)ne);
+    }
+  }
+}
+
+// Adjacency bitmap of hubs[s] (blockIdx.x = s): one bit per neighbour.
+__global__ __launch_bounds__(256) void k_hub_bitmaps(const int64_t *rp, const int32_t *col, const int32_t *hubs,
+                                                     int64_t nhubs, uint32_t *bits, uint64_t words) {
+  for (int64_t h = blockIdx.x; h < nhubs; h += gridDim.x) {
+    const int32_t v = hubs[h];
+    uint32_t *bm = bits + (uint64_t)h * words;
+    for (int64_t k = rp[v] + threadIdx.x; k < rp[v + 1]; k += blockDim.x) {
+      const uint32_t w = (uint32_t)col[k];
+      atomicOr(bm + (w >> 5), 1u << (w & 31));
     }
   }
 }
@@ -1072,6 +1088,20 @@ void launch_graph_stats(const gsm_graph &g, hipStream_t s) {
   hipLaunchKernelGGL(k_graph_stats, dim3(grid_for(g.n * 16, 256, 1u << 16)), dim3(256), 0, s,
                      g.rp, g.col, g.lab, g.n, g.deg, g.ne0, g.dne);
   GSM_HIP(hipGetLastError());
+}
+
+void launch_build_hub_bitmaps(const gsm_graph &g, const int32_t *hubs, int64_t nhubs, hipStream_t s) {
+  if (nhubs <= 0) return;
+  hipLaunchKernelGGL(k_hub_bitmaps, dim3((uint32_t)std::min<int64_t>(nhubs, 65535)), dim3(256), 0, s, g.rp, g.col,
+                     hubs, nhubs, g.hub_bits, g.hub_words);
+  GSM_HIP(hipGetLastError());
+}
+
+DeviceGraph device_graph(const gsm_graph &g) {
+  return DeviceGraph{g.rp,     g.col,      g.lab,         g.deg,  g.ne0,
+                     g.dne,    g.col_lab ? g.col_lab : g.col,     g.loff, g.loff_stride,
+                     g.n,      g.elab,     g.elab_lab ? g.elab_lab : g.elab,
+                     g.hub_slot, g.hub_bits, g.hub_words};
 }
 
 void launch_filter_init(const DeviceGraph &g, const QueryArgs &qa, uint16_t *cmask, hipStream_t s) {

@@ -127,8 +127,7 @@ struct Matcher {
   Matcher(gsm_graph &g_, const gsm_query &q_, const Options &o_, Workspace &ws_)
       : g(g_), qh(q_), o(o_), ws(ws_), s(o_.stream) {
     p = make_plan(g, qh);
-    dg = DeviceGraph{g.rp,  g.col,  g.lab, g.deg, g.ne0, g.dne, g.col_lab ? g.col_lab : g.col,
-                     g.loff, g.loff_stride, g.n, g.elab, g.elab_lab ? g.elab_lab : g.elab};
+    dg = device_graph(g);
     dcnt = ws.counters.as<uint64_t>();
     std::memset(&st, 0, sizeof(st));
     st.struct_size = sizeof(st);
