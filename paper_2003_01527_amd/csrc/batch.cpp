@@ -40,6 +40,7 @@ struct BatchMatcher {
   uint64_t *dcnt;
   BatchLevel *d_bl = nullptr;
   FirstBatch *d_fb = nullptr;
+  int64_t max_class = 0;  // the largest label class a first frontier scans
   uint64_t *d_counts = nullptr;
   uint64_t launches = 0;
   uint64_t level_pairs[kMaxQ] = {0};
@@ -123,6 +124,17 @@ struct BatchMatcher {
       fb[k].qne0 = use_ne ? std::min<uint64_t>(p.qne[u0], 0xffffffffull) : 0;
       fb[k].label1 = (p.q > 1) ? p.qlab[p.order[1]] : 0;
       fb[k].single = (p.q == 1) ? 1 : 0;
+      // the label class the first frontier scans (empty for a label the graph lacks)
+      const int32_t l0 = fb[k].qlab0;
+      if (g.lab_vert) {
+        const bool has = l0 >= 0 && (size_t)l0 + 1 < g.lab_start.size();
+        fb[k].vbegin = has ? g.lab_start[l0] : 0;
+        fb[k].vend = has ? g.lab_start[l0 + 1] : 0;
+      } else {
+        fb[k].vbegin = 0;
+        fb[k].vend = l0 == 0 ? g.n : 0;
+      }
+      max_class = std::max<int64_t>(max_class, fb[k].vend - fb[k].vbegin);
     }
     const size_t b_bl = bl.size() * sizeof(BatchLevel), b_fb = nq * sizeof(FirstBatch);
     const size_t o_fb = (b_bl + 255) & ~size_t(255);
@@ -252,7 +264,7 @@ struct BatchMatcher {
     upload_tables();
     launch_zero_u64(dcnt, 64, s);
     reserve_level(1, cap[1]);
-    launch_compact_first_batch(dg, d_fb, nq, ws.rows[1].as<int32_t>(),
+    launch_compact_first_batch(dg, d_fb, nq, max_class, ws.rows[1].as<int32_t>(),
                                ws.qid[1].as<uint16_t>(), ws.W[1].as<uint32_t>(), ws.abase[1].as<int64_t>(),
                                ws.apos[1].as<uint8_t>(), dcnt + kCntRows + 1, d_counts, nullptr, s);
     stack.clear();
@@ -338,7 +350,7 @@ struct BatchMatcher {
     uint32_t *overflow = reinterpret_cast<uint32_t *>(dcnt + kCntOverflow);
     launch_zero_u64(dcnt, 64, st);
     if (evict_pairs) launch_zero_u64(ws.evicted.as<uint64_t>(), (nq + 1 + 7) / 8, st);
-    launch_compact_first_batch(dg, d_fb, nq, ws.rows[1].as<int32_t>(), ws.qid[1].as<uint16_t>(),
+    launch_compact_first_batch(dg, d_fb, nq, max_class, ws.rows[1].as<int32_t>(), ws.qid[1].as<uint16_t>(),
                                ws.W[1].as<uint32_t>(), ws.abase[1].as<int64_t>(), ws.apos[1].as<uint8_t>(),
                                dcnt + kCntRows + 1, d_counts, nullptr, st);
     for (int i = 1; i < maxq; ++i) {
@@ -383,6 +395,7 @@ struct BatchMatcher {
     put(&dg, sizeof(dg));
     put(&nq, sizeof(nq));
     put(&maxq, sizeof(maxq));
+    put(&max_class, sizeof(max_class));
     put(dev_cap, sizeof(dev_cap));
     put(&wg, sizeof(wg));
     put(&items, sizeof(items));
@@ -460,7 +473,7 @@ struct BatchMatcher {
   std::vector<uint64_t> first_level_pairs() {
     upload_tables();
     launch_zero_u64(d_counts, std::max(nq, 1), s);
-    launch_compact_first_batch(dg, d_fb, nq, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+    launch_compact_first_batch(dg, d_fb, nq, max_class, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                nullptr, d_counts, s);
     std::vector<uint64_t> out(nq);
     GSM_HIP(hipMemcpyAsync(out.data(), d_counts, nq * sizeof(uint64_t), hipMemcpyDeviceToHost, s));

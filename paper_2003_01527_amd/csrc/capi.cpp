@@ -451,6 +451,17 @@ gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t 
       if (d > gsm::kHeavyDegree) heavy.push_back((int32_t)v);
       g->label_count[h_lab ? h_lab[v] : 0]++;
     }
+    // vertices grouped by label, ascending within a label: a batched first
+    // frontier scans only the class of its first query vertex
+    g->lab_start.assign((size_t)max_label + 2, 0);
+    for (int32_t l = 0; l <= max_label; ++l) g->lab_start[l + 1] = g->lab_start[l] + g->label_count[l];
+    if (h_lab && n > 0) {
+      std::vector<int32_t> by_label((size_t)n);
+      std::vector<int64_t> at(g->lab_start.begin(), g->lab_start.end() - 1);
+      for (int64_t v = 0; v < n; ++v) by_label[at[h_lab[v]]++] = (int32_t)v;
+      gsm::device_alloc((void **)&g->lab_vert, (size_t)n * sizeof(int32_t));
+      GSM_HIP(hipMemcpy(g->lab_vert, by_label.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     g->max_degree = maxd;
     g->deg_ge.assign((size_t)maxd + 2, 0);
     for (int64_t v = 0; v < n; ++v) g->deg_ge[h_rp[v + 1] - h_rp[v]]++;
@@ -526,6 +537,7 @@ void gsm_graph_destroy(gsm_graph_t g) {
   (void)hipFree(g->heavy);
   (void)hipFree(g->hub_slot);
   (void)hipFree(g->hub_bits);
+  (void)hipFree(g->lab_vert);
   (void)hipFree(g->col_lab);
   (void)hipFree(g->loff);
   (void)hipFree(g->elab);

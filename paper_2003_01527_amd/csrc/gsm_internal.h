@@ -96,6 +96,10 @@ struct gsm_graph {
   uint32_t *hub_bits = nullptr;
   uint64_t hub_words = 0;
   int64_t nhubs = 0;
+  // vertices sorted by label (labelled graphs): the vertices of label l are
+  // lab_vert[lab_start[l] .. lab_start[l+1])
+  int32_t *lab_vert = nullptr;
+  std::vector<int64_t> lab_start;
   // label-grouped adjacency (labelled graphs with at most kMaxTableLabels labels):
   // row v of col_lab holds v's neighbours sorted by (label, id), and
   // loff[v * loff_stride + l] is where label l starts inside that row.
@@ -231,6 +235,7 @@ struct DeviceGraph {
   const int32_t *hub_slot;     // bitmap index per vertex (-1: none), or null
   const uint32_t *hub_bits;
   uint64_t hub_words;
+  const int32_t *lab_vert;     // vertices sorted by label, or null
 };
 
 // Each launcher enqueues on `s` and returns immediately.
@@ -357,11 +362,12 @@ struct FirstBatch {
   int32_t label1;     // label of position 1 (unused when q == 1)
   int32_t single;     // q == 1
   uint32_t slice_mod, slice_rem;  // root slice on position 0 (slice_mod 0 = none)
+  int64_t vbegin, vend;           // the label class of position 0 in lab_vert (or [0, n))
 };
-void launch_compact_first_batch(const DeviceGraph &g, const FirstBatch *fb_dev,
-                                int nq, int32_t *rows, uint16_t *qid, uint32_t *W, int64_t *abase,
-                                uint8_t *apos, uint64_t *counter, uint64_t *counts, uint64_t *pairs1,
-                                hipStream_t s);
+// max_class: the largest vend - vbegin over the queries (sizes the grid).
+void launch_compact_first_batch(const DeviceGraph &g, const FirstBatch *fb_dev, int nq, int64_t max_class,
+                                int32_t *rows, uint16_t *qid, uint32_t *W, int64_t *abase, uint8_t *apos,
+                                uint64_t *counter, uint64_t *counts, uint64_t *pairs1, hipStream_t s);
 // The single-query entry: gsm_match (fixed_ws = null: the graph's workspace,
 // under its lock) or gsm_match_noalloc (a fixed workspace over the
 // no-allocation scratch).

@@ -364,57 +364,65 @@ __device__ __forceinline__ bool inline_candidate(const DeviceGraph &g, int32_t v
 
 // rows == null: estimate only, adding each query's first-level pair total
 // (the sum of its rows' range sizes) to pairs1[k] and writing nothing else.
+// The candidates of position 0 of query k (blockIdx.y) among the vertices
+// of its label class (vertices sorted by label, or all vertices when the
+// graph has no such index): first-frontier rows, or (rows == null) only the
+// query's first-level pair total, or (a one-vertex query) its count.  Each
+// block aggregates its survivors before one atomic.
 __global__ __launch_bounds__(256) void k_compact_first_batch(DeviceGraph g, const FirstBatch *fb_all,
                                                              int32_t *rows,
                                                              uint16_t *qid, uint32_t *W, int64_t *abase,
                                                              uint8_t *apos, uint64_t *counter,
                                                              uint64_t *counts, uint64_t *pairs1) {
+  __shared__ uint64_t sw[256 / kWave];
+  __shared__ uint64_t s_base;
   const int k = blockIdx.y;
   const FirstBatch fb = fb_all[k];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & (kWave - 1);
-  uint32_t single = 0;
-  for (int64_t vb = start - lane; vb < g.n; vb += stride) {
-    const int64_t v = vb + lane;
+  const int64_t len = fb.vend - fb.vbegin;
+  uint64_t tally = 0;  // single: vertices kept; estimate: pairs
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < len; i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t idx = i0 + threadIdx.x;
     bool keep = false;
     uint32_t d = 0;
     int64_t b = 0;
-    if (v < g.n) {
-      keep = inline_candidate(g, (int32_t)v, fb.qlab0, fb.qdeg0, fb.qne0, false);
+    int32_t v = 0;
+    if (idx < len) {
+      v = g.lab_vert ? g.lab_vert[fb.vbegin + idx] : (int32_t)(fb.vbegin + idx);
+      keep = inline_candidate(g, v, fb.qlab0, fb.qdeg0, fb.qne0, g.lab_vert != nullptr);
       if (keep && fb.slice_mod) keep = slice_mix((uint64_t)v) % fb.slice_mod == fb.slice_rem;
       if (keep && !fb.single) {
-        d = label_range(g, (int32_t)v, fb.label1, b);
+        d = label_range(g, v, fb.label1, b);
         keep = d > 0;
       }
     }
-    const uint64_t mask = wave_ballot(keep);
-    if (mask == 0) continue;
-    if (fb.single) {
-      single += (uint32_t)__popcll(mask);
+    if (fb.single || !rows) {
+      tally += fb.single ? (uint64_t)keep : (keep ? d : 0);
       continue;
     }
-    if (!rows) {
-      uint64_t sum = keep ? d : 0;
-#pragma unroll
-      for (int o = kWave / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, kWave);
-      if (lane == 0) atomicAdd((unsigned long long *)(pairs1 + k), (unsigned long long)sum);
-      continue;
-    }
-    uint64_t base = 0;
-    if (lane == 0) base = atomicAdd((unsigned long long *)counter, (unsigned long long)__popcll(mask));
-    base = __shfl(base, 0, kWave);
+    uint64_t total;
+    const uint64_t before = block_excl_scan<256>(keep ? 1u : 0u, sw, &total);
+    if (total == 0) continue;  // uniform: every thread has the same total
+    if (threadIdx.x == 0) s_base = atomicAdd((unsigned long long *)counter, (unsigned long long)total);
+    __syncthreads();
+    const uint64_t base = s_base;
     if (keep) {
-      const uint64_t pos = base + lane_prefix(mask);
-      rows[pos] = (int32_t)v;
+      const uint64_t pos = base + before;
+      rows[pos] = v;
       qid[pos] = (uint16_t)k;
       W[pos] = d;
       abase[pos] = b;
       apos[pos] = 0;
     }
+    __syncthreads();  // s_base is rewritten by the next iteration
   }
-  if (fb.single && lane == 0 && single && counts)
-    atomicAdd((unsigned long long *)(counts + k), (unsigned long long)single);
+  if (fb.single || !rows) {
+    uint64_t total;
+    block_excl_scan<256>(tally, sw, &total);
+    if (threadIdx.x == 0 && total) {
+      if (fb.single && counts) atomicAdd((unsigned long long *)(counts + k), (unsigned long long)total);
+      if (!fb.single && !rows) atomicAdd((unsigned long long *)(pairs1 + k), (unsigned long long)total);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ scan --
@@ -1101,7 +1109,7 @@ DeviceGraph device_graph(const gsm_graph &g) {
   return DeviceGraph{g.rp,     g.col,      g.lab,         g.deg,  g.ne0,
                      g.dne,    g.col_lab ? g.col_lab : g.col,     g.loff, g.loff_stride,
                      g.n,      g.elab,     g.elab_lab ? g.elab_lab : g.elab,
-                     g.hub_slot, g.hub_bits, g.hub_words};
+                     g.hub_slot, g.hub_bits, g.hub_words, g.lab_vert};
 }
 
 void launch_filter_init(const DeviceGraph &g, const QueryArgs &qa, uint16_t *cmask, hipStream_t s) {
@@ -1149,11 +1157,11 @@ void launch_scan(const uint32_t *W, const uint64_t *n_dev, uint64_t *S, uint64_t
   GSM_HIP(hipGetLastError());
 }
 
-void launch_compact_first_batch(const DeviceGraph &g, const FirstBatch *fb_dev, int nq, int32_t *rows,
-                                uint16_t *qid, uint32_t *W, int64_t *abase, uint8_t *apos,
+void launch_compact_first_batch(const DeviceGraph &g, const FirstBatch *fb_dev, int nq, int64_t max_class,
+                                int32_t *rows, uint16_t *qid, uint32_t *W, int64_t *abase, uint8_t *apos,
                                 uint64_t *counter, uint64_t *counts, uint64_t *pairs1, hipStream_t s) {
   if (g.n == 0 || nq == 0) return;
-  hipLaunchKernelGGL(k_compact_first_batch, dim3(grid_for(g.n, 256, 1024), nq), dim3(256), 0, s, g, fb_dev,
+  hipLaunchKernelGGL(k_compact_first_batch, dim3(grid_for(max_class, 256, 1024), nq), dim3(256), 0, s, g, fb_dev,
                      rows, qid, W, abase, apos, counter, counts, pairs1);
   GSM_HIP(hipGetLastError());
 }
