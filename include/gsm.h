@@ -70,6 +70,7 @@ typedef enum gsm_status {
 #define GSM_GRAPH_DEVICE_PTRS 2u /* row_ptr, col, labels are device pointers */
 #define GSM_GRAPH_STRIP 4u       /* make the adjacency simple and undirected first */
 #define GSM_GRAPH_NO_HUB_BITMAPS 8u /* no adjacency bitmaps for high-degree vertices */
+#define GSM_GRAPH_DEGREE_ORDER 16u  /* store the graph renumbered by degree (see below) */
 
 /*
  * Uploads a data graph.  The graph must be simple and undirected: each edge
@@ -92,6 +93,19 @@ typedef enum gsm_status {
  * vertex of degree >= 2048, highest degree first, while they fit 512 MiB:
  * an edge check against such a vertex is then one load instead of a search
  * of its sorted list (results are the same).
+ * GSM_GRAPH_DEGREE_ORDER stores the graph with its vertices renumbered by
+ * ascending degree (ties by id), on the host at creation (O(m log d), host
+ * threads; offsets and ids are range-checked, GSM_E_BAD_GRAPH otherwise).
+ * On skewed graphs whose ids carry no order (e.g. randomly permuted R-MAT)
+ * the vertices that edge checks test most often then sit together, so the
+ * words of adjacency bitmaps and the list entries those checks read share
+ * cache lines.  Every result is in the caller's ids: rows (translated back
+ * before they reach any sink or the row sort), candidate masks, and root
+ * slices (which hash the caller's ids).  One exception: in the
+ * unique-subgraph mode the embedding kept for each subgraph satisfies the
+ * ordering constraints in the internal order (degree, then id), so it can be
+ * another embedding of the same subgraph than without the flag; the count
+ * is the same.
  */
 gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col,
                             const int32_t *labels, uint32_t flags, gsm_graph_t *out);
@@ -253,7 +267,8 @@ typedef struct gsm_match_opts {
  * once by visiting equivalent query nodes in increasing id order, Sec. 3.3).
  * Embeddings f and f o s, s an automorphism of the query, are one subgraph;
  * the one kept satisfies the ordering constraints that gsm_query_symmetry
- * returns.  count = (count without the flag) / |Aut(Q)|.  Single-query
+ * returns (compared in the graph's internal order on a graph created with
+ * GSM_GRAPH_DEGREE_ORDER).  count = (count without the flag) / |Aut(Q)|.  Single-query
  * matching only (gsm_match_batch returns GSM_E_UNSUPPORTED). */
 #define GSM_MATCH_UNIQUE 8u
 /* Induced semantics (the other reading of subgraph isomorphism, Sec. 1):

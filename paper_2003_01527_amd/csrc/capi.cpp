@@ -3,6 +3,7 @@
 #include <atomic>
 #include <cstring>
 #include <new>
+#include <thread>
 
 #include "gsm_internal.h"
 
@@ -319,6 +320,68 @@ gsm_status gsm_query_symmetry(gsm_query_t qh, uint64_t *aut, int32_t *pairs, int
   GSM_API_END
 }
 
+// Renumbers a valid CSR by ascending degree, ties by id: orig[v'] is the
+// old id of new vertex v'; rows are rebuilt in the new numbering and sorted
+// (edge labels move with their entries).  Rows are split over host threads.
+static void renumber_by_degree(int64_t n, const int64_t *rp, const int32_t *col, const int32_t *lab,
+                               const int32_t *el, std::vector<int32_t> &orig, std::vector<int64_t> &nrp,
+                               std::vector<int32_t> &ncol, std::vector<int32_t> &nlab,
+                               std::vector<int32_t> &nel) {
+  int64_t maxd = 0;
+  for (int64_t v = 0; v < n; ++v) maxd = std::max(maxd, rp[v + 1] - rp[v]);
+  std::vector<int64_t> at((size_t)maxd + 2, 0);
+  for (int64_t v = 0; v < n; ++v) at[rp[v + 1] - rp[v] + 1]++;
+  for (int64_t d = 0; d <= maxd; ++d) at[d + 1] += at[d];
+  orig.assign((size_t)n, 0);
+  for (int64_t v = 0; v < n; ++v) orig[at[rp[v + 1] - rp[v]]++] = (int32_t)v;
+  std::vector<int32_t> newid((size_t)n);
+  for (int64_t v = 0; v < n; ++v) newid[orig[v]] = (int32_t)v;
+  nrp.assign((size_t)n + 1, 0);
+  for (int64_t v = 0; v < n; ++v) nrp[v + 1] = nrp[v] + (rp[orig[v] + 1] - rp[orig[v]]);
+  const int64_t nnz = nrp[n];
+  ncol.assign((size_t)nnz, 0);
+  if (el) nel.assign((size_t)nnz, 0);
+  if (lab) {
+    nlab.assign((size_t)n, 0);
+    for (int64_t v = 0; v < n; ++v) nlab[v] = lab[orig[v]];
+  }
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)(hw ? hw : 1), 16, nnz / 65536 + 1}));
+  std::vector<std::vector<uint64_t>> keys((size_t)nt);
+  if (el)
+    for (auto &k : keys) k.resize((size_t)maxd);
+  auto work = [&](int t) {
+    for (int64_t v = n * t / nt; v < n * (t + 1) / nt; ++v) {
+      const int64_t b = rp[orig[v]], d = rp[orig[v] + 1] - b, o = nrp[v];
+      if (el) {
+        uint64_t *kk = keys[t].data();
+        for (int64_t j = 0; j < d; ++j)
+          kk[j] = ((uint64_t)(uint32_t)newid[col[b + j]] << 32) | (uint32_t)el[b + j];
+        std::sort(kk, kk + d);
+        for (int64_t j = 0; j < d; ++j) {
+          ncol[o + j] = (int32_t)(kk[j] >> 32);
+          nel[o + j] = (int32_t)(uint32_t)kk[j];
+        }
+      } else {
+        for (int64_t j = 0; j < d; ++j) ncol[o + j] = newid[col[b + j]];
+        std::sort(ncol.begin() + o, ncol.begin() + o + d);
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  int started = 1;
+  for (; started < nt; ++started) {
+    try {
+      th.emplace_back(work, started);
+    } catch (...) {
+      break;  // the ranges of threads that could not start run here
+    }
+  }
+  for (int t = started; t < nt; ++t) work(t);
+  work(0);
+  for (auto &x : th) x.join();
+}
+
 gsm_status gsm_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col,
                             const int32_t *labels, uint32_t flags, gsm_graph_t *out) {
   return gsm_graph_create_ex(n, row_ptr, col, labels, nullptr, flags, out);
@@ -351,7 +414,7 @@ gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t 
       gsm::set_error("row_ptr[n] < 0");
       return GSM_E_BAD_GRAPH;
     }
-    if ((flags & (GSM_GRAPH_VALIDATE | GSM_GRAPH_STRIP)) || labels || edge_labels) {
+    if ((flags & (GSM_GRAPH_VALIDATE | GSM_GRAPH_STRIP | GSM_GRAPH_DEGREE_ORDER)) || labels || edge_labels) {
       h_col_store.resize(nnz);
       if (nnz)
         GSM_HIP(hipMemcpy(h_col_store.data(), col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -422,13 +485,40 @@ gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t 
       }
       max_label = std::max(max_label, h_lab[v]);
     }
+  // GSM_GRAPH_DEGREE_ORDER: the graph is stored renumbered by ascending
+  // degree (ties by id), rows re-sorted in the new numbering
+  const bool reorder = (flags & GSM_GRAPH_DEGREE_ORDER) && n > 0;
+  std::vector<int32_t> orig_of;
+  std::vector<int64_t> re_rp;
+  std::vector<int32_t> re_col, re_lab, re_el;
+  if (reorder) {
+    // the renumbering indexes by offsets and ids: check their ranges even
+    // without GSM_GRAPH_VALIDATE
+    for (int64_t v = 0; v < n; ++v)
+      if (h_rp[v + 1] < h_rp[v] || h_rp[0] != 0) {
+        gsm::set_error("row_ptr is not non-decreasing from 0");
+        return GSM_E_BAD_GRAPH;
+      }
+    for (int64_t k = 0; k < nnz; ++k)
+      if (h_col[k] < 0 || h_col[k] >= n) {
+        gsm::set_error("neighbour id out of range at CSR entry " + std::to_string(k));
+        return GSM_E_BAD_GRAPH;
+      }
+    renumber_by_degree(n, h_rp, h_col, h_lab, h_el, orig_of, re_rp, re_col, re_lab, re_el);
+    h_rp = src_rp = re_rp.data();
+    h_col = src_col = re_col.data();
+    csr_kind = hipMemcpyHostToDevice;
+    if (h_lab) h_lab = re_lab.data();
+    if (h_el) h_el = re_el.data();
+  }
+  const int32_t *lab_src = reorder ? h_lab : labels;
   auto g = new gsm_graph();
   try {
     g->n = n;
     g->nnz = nnz;
     g->labelled = labels != nullptr;
     g->max_label = max_label;
-    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const hipMemcpyKind kind = (dev && !reorder) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     gsm::device_alloc((void **)&g->rp, (n + 1) * sizeof(int64_t));
     GSM_HIP(hipMemcpy(g->rp, src_rp, (n + 1) * sizeof(int64_t), csr_kind));
     gsm::device_alloc((void **)&g->col, std::max<int64_t>(nnz, 1) * sizeof(int32_t));
@@ -437,7 +527,7 @@ gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t 
     gsm::device_alloc((void **)&g->dne, std::max<int64_t>(n, 1) * sizeof(uint2));
     if (labels) {
       gsm::device_alloc((void **)&g->lab, std::max<int64_t>(n, 1) * sizeof(int32_t));
-      if (n) GSM_HIP(hipMemcpy(g->lab, labels, n * sizeof(int32_t), kind));
+      if (n) GSM_HIP(hipMemcpy(g->lab, lab_src, n * sizeof(int32_t), kind));
       gsm::device_alloc((void **)&g->ne0, std::max<int64_t>(n, 1) * sizeof(uint64_t));
     }
     gsm::launch_graph_stats(*g, nullptr);
@@ -514,6 +604,11 @@ gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t 
         if (e != hipSuccess) throw Error{GSM_E_DEVICE, std::string("hub bitmaps: ") + hipGetErrorString(e)};
       }
     }
+    if (reorder) {
+      gsm::device_alloc((void **)&g->orig, (size_t)n * sizeof(int32_t));
+      GSM_HIP(hipMemcpy(g->orig, orig_of.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice));
+      g->h_orig = std::move(orig_of);
+    }
     GSM_HIP(hipDeviceSynchronize());
   } catch (...) {
     gsm_graph_destroy(g);
@@ -538,6 +633,7 @@ void gsm_graph_destroy(gsm_graph_t g) {
   (void)hipFree(g->hub_slot);
   (void)hipFree(g->hub_bits);
   (void)hipFree(g->lab_vert);
+  (void)hipFree(g->orig);
   (void)hipFree(g->col_lab);
   (void)hipFree(g->loff);
   (void)hipFree(g->elab);

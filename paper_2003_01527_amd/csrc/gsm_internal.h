@@ -100,6 +100,11 @@ struct gsm_graph {
   // lab_vert[lab_start[l] .. lab_start[l+1])
   int32_t *lab_vert = nullptr;
   std::vector<int64_t> lab_start;
+  // GSM_GRAPH_DEGREE_ORDER: vertices renumbered by ascending degree; every
+  // array above is in the internal numbering and orig[v] is the caller's id of
+  // internal vertex v (device and host copies); null / empty otherwise
+  int32_t *orig = nullptr;
+  std::vector<int32_t> h_orig;
   // label-grouped adjacency (labelled graphs with at most kMaxTableLabels labels):
   // row v of col_lab holds v's neighbours sorted by (label, id), and
   // loff[v * loff_stride + l] is where label l starts inside that row.
@@ -236,10 +241,13 @@ struct DeviceGraph {
   const uint32_t *hub_bits;
   uint64_t hub_words;
   const int32_t *lab_vert;     // vertices sorted by label, or null
+  const int32_t *orig;         // caller's id of each vertex when renumbered by degree, or null
 };
 
 // Each launcher enqueues on `s` and returns immediately.
 void launch_graph_stats(const gsm_graph &g, hipStream_t s);
+// ids[k] = orig[ids[k]] for k < count (rows back to the caller's vertex ids)
+void launch_map_ids(int32_t *ids, uint64_t count, const int32_t *orig, hipStream_t s);
 void launch_filter_init(const DeviceGraph &g, const QueryArgs &qa, uint16_t *cmask, hipStream_t s);
 void launch_filter_refine(const DeviceGraph &g, const int32_t *heavy, int64_t nheavy,
                           const QueryArgs &qa, const uint16_t *prev, uint16_t *next, hipStream_t s);

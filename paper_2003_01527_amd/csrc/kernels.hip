@@ -146,6 +146,11 @@ __global__ __launch_bounds__(256) void k_hub_bitmaps(const int64_t *rp, const in
 
 // ---------------------------------------------------------------- filter --
 
+// The id a root slice hashes: the caller's id of v.
+__device__ __forceinline__ uint64_t slice_id(const DeviceGraph &g, int32_t v) {
+  return (uint64_t)(uint32_t)(g.orig ? g.orig[v] : v);
+}
+
 __device__ __forceinline__ uint16_t candidate_bits(const QueryArgs &qa, int32_t lv, uint32_t d,
                                                    uint64_t ne, uint64_t v) {
   uint32_t m = 0;
@@ -165,7 +170,7 @@ __global__ void k_filter_init(DeviceGraph g, QueryArgs qa, uint16_t *cmask) {
     const int32_t lv = g.lab ? g.lab[v] : 0;
     const uint32_t d = g.deg[v];
     const uint64_t ne = g.ne0 ? g.ne0[v] : (uint64_t)d;
-    cmask[v] = candidate_bits(qa, lv, d, ne, (uint64_t)v);
+    cmask[v] = candidate_bits(qa, lv, d, ne, slice_id(g, (int32_t)v));
   }
 }
 
@@ -389,7 +394,7 @@ __global__ __launch_bounds__(256) void k_compact_first_batch(DeviceGraph g, cons
     if (idx < len) {
       v = g.lab_vert ? g.lab_vert[fb.vbegin + idx] : (int32_t)(fb.vbegin + idx);
       keep = inline_candidate(g, v, fb.qlab0, fb.qdeg0, fb.qne0, g.lab_vert != nullptr);
-      if (keep && fb.slice_mod) keep = slice_mix((uint64_t)v) % fb.slice_mod == fb.slice_rem;
+      if (keep && fb.slice_mod) keep = slice_mix(slice_id(g, v)) % fb.slice_mod == fb.slice_rem;
       if (keep && !fb.single) {
         d = label_range(g, v, fb.label1, b);
         keep = d > 0;
@@ -684,7 +689,7 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
           cand[it] = dn[it].x >= bl[it].qdeg && (uint64_t)dn[it].y >= bl[it].qne &&
                      (label_known || lv[it] == bl[it].qlab);
           if (bl[it].slice_mod && cand[it])
-            cand[it] = slice_mix((uint64_t)(uint32_t)wv[it]) % bl[it].slice_mod == bl[it].slice_rem;
+            cand[it] = slice_mix(slice_id(a.g, wv[it])) % bl[it].slice_mod == bl[it].slice_rem;
         }
       } else {
         uint32_t cm[ITEMS];
@@ -1013,6 +1018,23 @@ __global__ void k_zero_u64(uint64_t *p, size_t count) {
     p[k] = 0;
 }
 
+// Rows back to the caller's ids: 16-byte groups where the buffer allows.
+__global__ void k_map_ids(int32_t *ids, uint64_t count, const int32_t *__restrict__ orig) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t quads = ((uintptr_t)ids & 15) ? 0 : count / 4;
+  int4 *q4 = reinterpret_cast<int4 *>(ids);
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < quads; k += stride) {
+    int4 v = q4[k];
+    v.x = orig[v.x];
+    v.y = orig[v.y];
+    v.z = orig[v.z];
+    v.w = orig[v.w];
+    q4[k] = v;
+  }
+  for (uint64_t k = quads * 4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride)
+    ids[k] = orig[ids[k]];
+}
+
 constexpr size_t kMaxStageBytes = kExpandStageBytes;
 
 template <int WG, int ITEMS>
@@ -1091,6 +1113,13 @@ uint32_t grid_for(int64_t work, int wg, uint32_t cap) {
 
 // --------------------------------------------------------------- launchers --
 
+void launch_map_ids(int32_t *ids, uint64_t count, const int32_t *orig, hipStream_t s) {
+  if (count == 0 || !orig) return;
+  hipLaunchKernelGGL(k_map_ids, dim3(grid_for((int64_t)((count + 3) / 4), 256, 8192)), dim3(256), 0, s, ids, count,
+                     orig);
+  GSM_HIP(hipGetLastError());
+}
+
 void launch_graph_stats(const gsm_graph &g, hipStream_t s) {
   if (g.n == 0) return;
   hipLaunchKernelGGL(k_graph_stats, dim3(grid_for(g.n * 16, 256, 1u << 16)), dim3(256), 0, s,
@@ -1109,7 +1138,7 @@ DeviceGraph device_graph(const gsm_graph &g) {
   return DeviceGraph{g.rp,     g.col,      g.lab,         g.deg,  g.ne0,
                      g.dne,    g.col_lab ? g.col_lab : g.col,     g.loff, g.loff_stride,
                      g.n,      g.elab,     g.elab_lab ? g.elab_lab : g.elab,
-                     g.hub_slot, g.hub_bits, g.hub_words, g.lab_vert};
+                     g.hub_slot, g.hub_bits, g.hub_words, g.lab_vert, g.orig};
 }
 
 void launch_filter_init(const DeviceGraph &g, const QueryArgs &qa, uint16_t *cmask, hipStream_t s) {

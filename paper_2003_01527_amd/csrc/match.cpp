@@ -380,6 +380,7 @@ struct Matcher {
   // Hands staged rows [0, nrows) to the sink.
   void drain_stage(uint64_t nrows) {
     if (nrows == 0) return;
+    launch_map_ids(ws.emit.as<int32_t>(), nrows * (uint64_t)p.q, g.orig, s);  // no-op without renumbering
     if (o.emit && o.rows_dev) {  // device sink: the callback reads device memory
       sync();
       if (o.emit(o.emit_ctx, ws.emit.as<int32_t>(), nrows, p.q) != 0) cancelled = true;
@@ -716,6 +717,7 @@ gsm_status match_call(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts,
     m.finish_stats(c);
     *count = c;
     const uint64_t written = rows ? std::min(c, rows_cap) : 0;
+    if (!m.emit_host && written) launch_map_ids(rows, written * (uint64_t)qh->q, g->orig, m.s);
     if (o.sort && written > 1) sort_rows(rows, written, qh->q, g->n, o.rows_dev, ws.sort, m.s);
     if (rows_written) *rows_written = written;
     if (o.stats) {
@@ -773,6 +775,10 @@ gsm_status gsm_filter(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts,
     if (g->n)
       GSM_HIP(hipMemcpyAsync(cmask, ws.cmask.ptr, g->n * sizeof(uint16_t), hipMemcpyDeviceToHost, m.s));
     m.sync();
+    if (!g->h_orig.empty()) {  // back to the caller's vertex order
+      std::vector<uint16_t> t(cmask, cmask + g->n);
+      for (int64_t v = 0; v < g->n; ++v) cmask[g->h_orig[v]] = t[v];
+    }
     return GSM_OK;
   } catch (const Error &e) {
     gsm::set_error(e.msg);

@@ -23,6 +23,7 @@ GRAPH_VALIDATE = 1
 GRAPH_DEVICE_PTRS = 2
 GRAPH_STRIP = 4
 GRAPH_NO_HUB_BITMAPS = 8
+GRAPH_DEGREE_ORDER = 16
 
 STATUS = {0: "GSM_OK", 1: "GSM_E_INVALID_ARG", 2: "GSM_E_BAD_GRAPH", 3: "GSM_E_BAD_QUERY",
           4: "GSM_E_OOM", 5: "GSM_E_BUDGET", 6: "GSM_E_DEVICE", 7: "GSM_E_TRUNCATED",
@@ -158,10 +159,10 @@ class Graph:
     """A data graph uploaded to the device (simple, undirected, sorted CSR)."""
 
     def __init__(self, row_ptr, col, labels=None, validate: bool = False, strip: bool = False,
-                 edge_labels=None, hub_bitmaps: bool = True):
+                 edge_labels=None, hub_bitmaps: bool = True, degree_order: bool = False):
         lib = _load()
         flags = ((GRAPH_VALIDATE if validate else 0) | (GRAPH_STRIP if strip else 0)
-                 | (0 if hub_bitmaps else GRAPH_NO_HUB_BITMAPS))
+                 | (0 if hub_bitmaps else GRAPH_NO_HUB_BITMAPS) | (GRAPH_DEGREE_ORDER if degree_order else 0))
         self._h = ctypes.c_void_p()
         if hasattr(row_ptr, "data_ptr"):  # torch tensors on the device
             flags |= GRAPH_DEVICE_PTRS
@@ -179,9 +180,9 @@ class Graph:
         self.n = n
 
     @classmethod
-    def from_workload(cls, g, validate: bool = False, hub_bitmaps: bool = True):
+    def from_workload(cls, g, validate: bool = False, hub_bitmaps: bool = True, degree_order: bool = False):
         return cls(g.row_ptr, g.col, g.labels, validate, edge_labels=getattr(g, "edge_labels", None),
-                   hub_bitmaps=hub_bitmaps)
+                   hub_bitmaps=hub_bitmaps, degree_order=degree_order)
 
     def info(self):
         n, nnz, ml, md = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()

@@ -96,6 +96,7 @@ def test_binding_flags_match_header():
     assert defs["GSM_GRAPH_DEVICE_PTRS"] == gsm.GRAPH_DEVICE_PTRS
     assert defs["GSM_GRAPH_STRIP"] == gsm.GRAPH_STRIP
     assert defs["GSM_GRAPH_NO_HUB_BITMAPS"] == gsm.GRAPH_NO_HUB_BITMAPS
+    assert defs["GSM_GRAPH_DEGREE_ORDER"] == gsm.GRAPH_DEGREE_ORDER
     assert defs["GSM_MATCH_NO_OUTPUT_STAGING"] == gsm.FLAG_NO_OUTPUT_STAGING
     assert defs["GSM_MATCH_SORT_ROWS"] == gsm.FLAG_SORT_ROWS
     assert defs["GSM_MATCH_LOOKAHEAD"] == gsm.FLAG_LOOKAHEAD
