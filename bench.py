@@ -55,7 +55,12 @@ def traffic_record_path(workload):
     return os.path.join(ROOT, "profiles", "k_expand_%s_traffic.json" % workload)
 
 
-def measured_traffic(workload):
+VERTEX_ORDER = {False: "graph stored renumbered by ascending degree (GSM_GRAPH_DEGREE_ORDER); results in "
+                       "the generator's ids",
+                True: "graph stored in the generator's numbering"}
+
+
+def measured_traffic(workload, vertex_order):
     """HBM bytes per expansion launch from the committed rocprofv3 counter
     record of this workload, or None when any source it depends on changed
     since it was taken."""
@@ -64,10 +69,12 @@ def measured_traffic(workload):
         sha = sources_sha1()
     except (OSError, ValueError):
         return None
-    return rec["traffic_bytes_per_launch"] if rec.get("sources_sha1") == sha else None
+    if rec.get("sources_sha1") != sha or rec.get("vertex_order") != vertex_order:
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
-def write_traffic_record(workload, fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes):
+def write_traffic_record(workload, vertex_order, fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes):
     """Builds the traffic record from four rocprofv3 --pmc runs (csv output):
     FETCH_SIZE and WRITE_SIZE of the bench command (k_expand dispatches), and
     of a plain device copy of copy_bytes bytes (the calibration: what each
@@ -93,7 +100,7 @@ def write_traffic_record(workload, fetch_dir, write_dir, cfetch_dir, cwrite_dir,
     fetch = f_kib * 1024.0 * fscale
     write = w_kib * 1024.0 * wscale
     launches = max(nf, 1)
-    rec = {"kernel": "k_expand", "workload": workload, "sources_sha1": sources_sha1(),
+    rec = {"kernel": "k_expand", "workload": workload, "vertex_order": vertex_order, "sources_sha1": sources_sha1(),
            "launches": launches, "fetch_bytes": round(fetch), "write_bytes": round(write),
            "traffic_bytes_per_launch": round((fetch + write) / launches),
            "fetch_scale": fscale, "write_scale": wscale, "dispatch_records": [nf, nw]}
@@ -158,6 +165,11 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON)")
     ap.add_argument("--batch-cap-log2", type=int, default=32,
                     help="batch: reject queries whose spanning-tree bound exceeds 2^N (20 = light mix)")
+    ap.add_argument("--vertex-order", choices=["auto", "degree", "caller"], default="auto",
+                    help="store the data graph renumbered by ascending degree (GSM_GRAPH_DEGREE_ORDER) or in "
+                         "the generator's numbering; auto: the generator's for the power-law listing (its "
+                         "2^17-vertex graph is cache-resident and translating 8 x 10^10 listed ids back costs "
+                         "more than locality gains), by degree for the others")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (calibrates "
                          "the HBM byte counters of rocprofv3) and exit")
@@ -165,9 +177,12 @@ def main():
                     help="rocprofv3 --pmc output folders of FETCH_SIZE and WRITE_SIZE for this workload "
                          "and for a --copy-gib 1 run: store the traffic record and exit")
     args = ap.parse_args()
+    if args.vertex_order == "auto":
+        args.vertex_order = "caller" if args.workload == "powerlaw" else "degree"
+    args.caller_ids = args.vertex_order == "caller"
 
     if args.write_traffic_record:
-        return write_traffic_record(args.workload, *args.write_traffic_record, copy_bytes=1 << 30)
+        return write_traffic_record(args.workload, args.vertex_order, *args.write_traffic_record, copy_bytes=1 << 30)
 
     if args.copy_gib > 0:
         import torch
@@ -209,7 +224,7 @@ def bench_powerlaw(args):
     torch.cuda.init()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    G = gsm.Graph.from_workload(w.graph)
+    G = gsm.Graph.from_workload(w.graph, degree_order=not args.caller_ids)
     Qs = [gsm.Query.from_workload(q) for q in queries]
     budget = int(args.budget_gb * (1 << 30))
 
@@ -252,7 +267,8 @@ def bench_powerlaw(args):
 
     value = tot_emb / elapsed
     achieved = (tot_bytes / 1e9) / (tot_ms / 1e3) if tot_ms > 0 else 0.0
-    traffic = measured_traffic("powerlaw") if args.mode == "enumerate" and not (args.wg or args.items) else None
+    traffic = (measured_traffic("powerlaw", args.vertex_order) if args.mode == "enumerate" and not (args.wg or args.items)
+               else None)
     roofline = {
         "kernel": "k_expand (expand-verify-compact)",
         "bound": "hbm",
@@ -303,6 +319,7 @@ def bench_powerlaw(args):
                         "%d random-walk induced queries, 5-6 vertices, 5-9 edges; %s"
                         % (len(queries), "full enumeration into HBM" if args.mode == "enumerate"
                            else "count only"),
+            "vertex_order": VERTEX_ORDER[args.caller_ids],
             "graph_vertices": w.graph.n,
             "graph_csr_entries": w.graph.nnz,
             "queries": len(queries),
@@ -335,7 +352,7 @@ def bench_large(args):
     log("workload %s: n=%d nnz=%d (%.1fs)" % (g.name, g.n, g.nnz, time.time() - t))
     torch.cuda.init()
     stream = torch.cuda.current_stream(torch.device("cuda:0"))
-    G = gsm.Graph.from_workload(g)
+    G = gsm.Graph.from_workload(g, degree_order=not args.caller_ids)
     budget = int(args.budget_gb * (1 << 30))
     Qs = [(name, gsm.Query.from_workload(W.shape(shape)), root, emit, uniq)
           for name, shape, root, emit, uniq in LARGE_STEP]
@@ -390,7 +407,7 @@ def bench_large(args):
         e["unique"] = uniq
     achieved = (tot_bytes / 1e9) / (tot_ms / 1e3) if tot_ms > 0 else 0.0
     launches = max(tot_launch, 1)
-    traffic = measured_traffic("large") if not (args.wg or args.items) else None
+    traffic = measured_traffic("large", args.vertex_order) if not (args.wg or args.items) else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -422,6 +439,7 @@ def bench_large(args):
                         "into HBM, triangles counted once per subgraph (not in value), 4-clique on the root slice "
                         "splitmix64(f(0)) %% 512 == 1, 5-cycle on %% 2^17 == 1, house+tail on %% 2^20 == 1, "
                         "counted",
+            "vertex_order": VERTEX_ORDER[args.caller_ids],
             "graph_vertices": g.n,
             "graph_csr_entries": g.nnz,
             "per_query": per,
@@ -461,7 +479,7 @@ def bench_batch(args):
 
     w = W.batch(cap=float(2 ** args.batch_cap_log2))
     torch.cuda.init()
-    G = gsm.Graph.from_workload(w.graph)
+    G = gsm.Graph.from_workload(w.graph, degree_order=not args.caller_ids)
     Qs = [gsm.Query.from_workload(q) for q in w.queries]
     budget = int(args.budget_gb * (1 << 30))
     stream = torch.cuda.current_stream().cuda_stream
@@ -508,6 +526,7 @@ def bench_batch(args):
         "config": {"workload": "batch: R-MAT 2^17 ef8, 16 Zipf labels; %d random-walk queries, 3-8 vertices, "
                                "edge density 0.3-1.0, spanning-tree bound <= 2^%d; count only"
                                % (len(Qs), args.batch_cap_log2),
+                   "vertex_order": VERTEX_ORDER[args.caller_ids],
                    "embeddings_per_step": int(ref.sum())},
         "per_launch_queries_per_s": round(qps_p, 1),
         "autotuned": best,
@@ -532,7 +551,7 @@ def bench_serving(args):
     log("serving workload: n=%d nnz=%d, %d arrivals from %d distinct queries (%.1fs)"
         % (w.graph.n, w.graph.nnz, len(w.queries), len({id(q) for q in w.queries}), time.time() - t))
     torch.cuda.init()
-    G = gsm.Graph.from_workload(w.graph)
+    G = gsm.Graph.from_workload(w.graph, degree_order=not args.caller_ids)
     pool = {}
     Qs = []
     for qr in w.queries:
@@ -587,7 +606,8 @@ def bench_serving(args):
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": "serving: R-MAT 2^20 ef12, 32 Zipf labels; %d Poisson arrivals of random-walk "
-                               "queries (3-8 vertices), count only; %d workers" % (len(Qs), args.workers)},
+                               "queries (3-8 vertices), count only; %d workers" % (len(Qs), args.workers),
+                   "vertex_order": VERTEX_ORDER[args.caller_ids]},
         "latency_at_0.8x_saturation": r08,
         "latency_at_0.5x_saturation": r05,
         "saturation": sat,

@@ -246,8 +246,6 @@ struct DeviceGraph {
 
 // Each launcher enqueues on `s` and returns immediately.
 void launch_graph_stats(const gsm_graph &g, hipStream_t s);
-// ids[k] = orig[ids[k]] for k < count (rows back to the caller's vertex ids)
-void launch_map_ids(int32_t *ids, uint64_t count, const int32_t *orig, hipStream_t s);
 void launch_filter_init(const DeviceGraph &g, const QueryArgs &qa, uint16_t *cmask, hipStream_t s);
 void launch_filter_refine(const DeviceGraph &g, const int32_t *heavy, int64_t nheavy,
                           const QueryArgs &qa, const uint16_t *prev, uint16_t *next, hipStream_t s);

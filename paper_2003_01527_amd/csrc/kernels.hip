@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void k_compact_first(DeviceGraph g, const uint
         abase[pos] = b;
         apos[pos] = 0;
       }
-      if (emit_rows && pos < emit_cap) emit_rows[pos] = (int32_t)v;
+      if (emit_rows && pos < emit_cap) emit_rows[pos] = g.orig ? g.orig[v] : (int32_t)v;  // caller's ids
     }
   }
 }
@@ -939,9 +939,11 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
             }
             // the row in output-column order, two columns per 8-byte store
             // when the row starts 8-byte aligned (global rows only)
+            // (emitted rows carry the caller's ids on a renumbered graph)
             auto colval = [&](int c) -> int32_t {
               const int j = kIdOrder ? c : a.L.in_pos[c];
-              return j == i ? w : (stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j]);
+              const int32_t x = j == i ? w : (stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j]);
+              return (!kIdOrder && a.g.orig) ? a.g.orig[x] : x;
             };
             int c = 0;
             if (!a.staged && ((uintptr_t)o & 7) == 0) {
@@ -1016,23 +1018,6 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
 __global__ void k_zero_u64(uint64_t *p, size_t count) {
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x)
     p[k] = 0;
-}
-
-// Rows back to the caller's ids: 16-byte groups where the buffer allows.
-__global__ void k_map_ids(int32_t *ids, uint64_t count, const int32_t *__restrict__ orig) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint64_t quads = ((uintptr_t)ids & 15) ? 0 : count / 4;
-  int4 *q4 = reinterpret_cast<int4 *>(ids);
-  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < quads; k += stride) {
-    int4 v = q4[k];
-    v.x = orig[v.x];
-    v.y = orig[v.y];
-    v.z = orig[v.z];
-    v.w = orig[v.w];
-    q4[k] = v;
-  }
-  for (uint64_t k = quads * 4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride)
-    ids[k] = orig[ids[k]];
 }
 
 constexpr size_t kMaxStageBytes = kExpandStageBytes;
@@ -1112,13 +1097,6 @@ uint32_t grid_for(int64_t work, int wg, uint32_t cap) {
 }  // namespace
 
 // --------------------------------------------------------------- launchers --
-
-void launch_map_ids(int32_t *ids, uint64_t count, const int32_t *orig, hipStream_t s) {
-  if (count == 0 || !orig) return;
-  hipLaunchKernelGGL(k_map_ids, dim3(grid_for((int64_t)((count + 3) / 4), 256, 8192)), dim3(256), 0, s, ids, count,
-                     orig);
-  GSM_HIP(hipGetLastError());
-}
 
 void launch_graph_stats(const gsm_graph &g, hipStream_t s) {
   if (g.n == 0) return;

@@ -380,7 +380,6 @@ struct Matcher {
   // Hands staged rows [0, nrows) to the sink.
   void drain_stage(uint64_t nrows) {
     if (nrows == 0) return;
-    launch_map_ids(ws.emit.as<int32_t>(), nrows * (uint64_t)p.q, g.orig, s);  // no-op without renumbering
     if (o.emit && o.rows_dev) {  // device sink: the callback reads device memory
       sync();
       if (o.emit(o.emit_ctx, ws.emit.as<int32_t>(), nrows, p.q) != 0) cancelled = true;
@@ -717,7 +716,6 @@ gsm_status match_call(gsm_graph_t g, gsm_query_t qh, const gsm_match_opts *opts,
     m.finish_stats(c);
     *count = c;
     const uint64_t written = rows ? std::min(c, rows_cap) : 0;
-    if (!m.emit_host && written) launch_map_ids(rows, written * (uint64_t)qh->q, g->orig, m.s);
     if (o.sort && written > 1) sort_rows(rows, written, qh->q, g->n, o.rows_dev, ws.sort, m.s);
     if (rows_written) *rows_written = written;
     if (o.stats) {

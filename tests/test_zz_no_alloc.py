@@ -104,3 +104,19 @@ def test_noalloc_rejects_oversize_graph_and_sort():
     with pytest.raises(gsm.GsmError) as ei:
         gsm.match_noalloc(Gs, Qs, rows=buf, sort_rows=True)
     assert ei.value.status == 9
+
+
+def test_noalloc_on_degree_ordered_graph():
+    # a graph stored renumbered by degree: rows still in the caller's ids,
+    # equal to gsm_match's and the oracle's
+    import torch
+    torch.cuda.init()
+    small = W.small()
+    G = gsm.Graph.from_workload(small.graph, degree_order=True)
+    for qs in small.queries[:3]:
+        print("degree order:", qs.name, flush=True)
+        Q = gsm.Query.from_workload(qs)
+        cn, rn = _device_rows(gsm.match_noalloc, G, Q, qs.q)
+        co, ro = oracle.match(small.graph, qs)
+        assert cn == co
+        np.testing.assert_array_equal(rn, ro)
