@@ -90,7 +90,8 @@ typedef enum gsm_status {
  *            the upload (GSM_E_BAD_GRAPH only for bad offsets or ids).
  * Also computes per-vertex degree and neighbourhood encoding on the device,
  * and, unless GSM_GRAPH_NO_HUB_BITMAPS, an adjacency bitmap (n bits) for each
- * vertex of degree >= 2048, highest degree first, while they fit 512 MiB:
+ * vertex of degree >= 512, highest degree first, while they fit 8 GiB and a
+ * quarter of the free device memory:
  * an edge check against such a vertex is then one load instead of a search
  * of its sorted list (results are the same).
  * GSM_GRAPH_DEGREE_ORDER stores the graph with its vertices renumbered by

@@ -570,7 +570,10 @@ gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t 
     if (!(flags & GSM_GRAPH_NO_HUB_BITMAPS) && n > 0) {
       // adjacency bitmaps of the highest-degree vertices, while they fit
       const uint64_t words = ((uint64_t)n + 31) / 32;
-      const uint64_t fit = gsm::kHubBitmapBytes / (words * 4);
+      uint64_t cap = gsm::kHubBitmapBytes;
+      size_t free_b = 0, total_b = 0;
+      if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) cap = std::min<uint64_t>(cap, free_b / 4);
+      const uint64_t fit = cap / (words * 4);
       std::vector<int32_t> hubs;
       for (int64_t v = 0; v < n; ++v)
         if (h_rp[v + 1] - h_rp[v] >= gsm::kHubMinDegree) hubs.push_back((int32_t)v);

@@ -138,9 +138,10 @@ namespace gsm {
 
 constexpr int64_t kHeavyDegree = 2048;
 // Vertices of at least this degree get an adjacency bitmap, highest degree
-// first, while the bitmaps fit kHubBitmapBytes.
-constexpr int64_t kHubMinDegree = 2048;
-constexpr uint64_t kHubBitmapBytes = uint64_t(512) << 20;
+// first, while the bitmaps fit kHubBitmapBytes and a quarter of the free
+// device memory.
+constexpr int64_t kHubMinDegree = 512;
+constexpr uint64_t kHubBitmapBytes = uint64_t(8) << 30;
 constexpr int32_t kMaxTableLabels = 64;
 
 // ------------------------------------------------------------------- plan --
