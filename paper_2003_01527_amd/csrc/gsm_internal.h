@@ -184,6 +184,7 @@ struct LevelArgs {
   int32_t q;
   uint32_t nbr_mask;       // positions j < i adjacent to position i
   uint32_t qbit;           // cmask bit (query id) of position i
+  uint32_t no_cmask;       // skip the candidate mask test of position i (it can only prune)
   uint32_t next_nbr_mask;  // positions j <= i adjacent to position i+1 (0 at the last level)
   int32_t next_label;      // label of position i+1
   int32_t out_col[kMaxQ];  // emit: output column (query id) of position j

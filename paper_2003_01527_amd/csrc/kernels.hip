@@ -693,8 +693,13 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
         }
       } else {
         uint32_t cm[ITEMS];
+        if (a.L.no_cmask) {
 #pragma unroll
-        for (int it = 0; it < ITEMS; ++it) cm[it] = a.cmask[wv[it]];
+          for (int it = 0; it < ITEMS; ++it) cm[it] = 0xffffu;
+        } else {
+#pragma unroll
+          for (int it = 0; it < ITEMS; ++it) cm[it] = a.cmask[wv[it]];
+        }
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
           p_nbr[it] = a.L.nbr_mask;

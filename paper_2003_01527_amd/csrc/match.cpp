@@ -305,6 +305,15 @@ struct Matcher {
     ws.S[i].reserve((rows + 1) * 8, s);
   }
 
+  // The last position's candidate test can only prune: its label is given
+  // by the label-grouped gather (or the graph has none), every edge to it
+  // and injectivity are checked explicitly, and the filter keeps every
+  // vertex of an embedding.  It is kept where it carries the root slice.
+  bool skips_mask(int i) const {
+    const int u = p.order[i];
+    return i + 1 == p.q && o.root_q != u && (g.loff || (!g.lab && p.qlab[u] == 0));
+  }
+
   LevelArgs level_args(int i) const {
     LevelArgs L;
     std::memset(&L, 0, sizeof(L));
@@ -318,6 +327,7 @@ struct Matcher {
       L.out_col[j] = p.order[j];
       L.in_pos[p.order[j]] = j;
     }
+    L.no_cmask = skips_mask(i) ? 1 : 0;
     if (o.induced) L.non_mask = ((1u << i) - 1u) & ~p.backmask[i];
     if (qh.has_elab) {
       L.use_elab = 1;
@@ -575,7 +585,7 @@ struct Matcher {
     uint64_t b = 0;
     for (int i = 1; i < p.q; ++i) {
       const uint64_t others = (uint64_t)std::max(0, __builtin_popcount(p.backmask[i]) - 1);
-      b += st.rows[i - 1] * (4ull * i + 8 + 8 * others) + st.pairs[i] * (4 + 2);
+      b += st.rows[i - 1] * (4ull * i + 8 + 8 * others) + st.pairs[i] * (skips_mask(i) ? 4 : 4 + 2);
       if (i + 1 < p.q) b += st.rows[i] * 4ull * (i + 1);
     }
     b += st.probes * 4;
