@@ -579,28 +579,43 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
         lo += k * step;
         hi = min(hi, lo + step);
       }
-      if (lane == 0) s_r0 = lo;
+      // rows touched: every row has at least one pair, so the first row
+      // starting at or after the tile's end e is within len rows of r0
+      // (S[r0+k] >= t0+k); the same search finds it in two rounds
+      const uint64_t e = t0 + len;
+      uint64_t lo2 = lo, hi2 = min(n_rows, lo + len);  // S[lo2] < e <= S[hi2]
+      while (hi2 - lo2 > 1) {
+        const uint64_t step = (hi2 - lo2 + kWave - 1) / kWave;
+        const uint64_t idx = lo2 + (uint64_t)lane * step;
+        const bool lt = idx < hi2 && a.S[idx] < e;  // true on lane 0
+        const uint64_t mask = wave_ballot(lt);
+        const uint64_t k = 63 - __builtin_clzll(mask);
+        lo2 += k * step;
+        hi2 = min(hi2, lo2 + step);
+      }
+      if (lane == 0) {
+        s_r0 = lo;
+        s_R = (uint32_t)(hi2 - lo);
+      }
     }
     __syncthreads();
     const uint64_t r0 = s_r0;
-    // window of row starts; row k intersects the tile iff sS[k] < len
-    for (int k = tid; k <= TILE; k += WG) {
-      const uint64_t r = r0 + k;
+    const uint32_t R = s_R;
+    // row starts relative to the tile: sS[k] <= t < sS[k+1] for the pairs t
+    // of row r0+k, k < R, and sS[R] >= len
+    for (uint32_t k = tid; k <= R; k += WG) {
       uint32_t rel;
       if (k == 0) {
         rel = 0;  // the first row may start before the tile: its lead is s_lead
         s_lead = (uint32_t)(t0 - a.S[r0]);
       } else {
-        const uint64_t v = (r <= n_rows) ? a.S[r] : ~0ull;
+        const uint64_t v = a.S[r0 + k];
         rel = (v - t0 > (uint64_t)TILE) ? (uint32_t)TILE + 1 : (uint32_t)(v - t0);
       }
       sS[k] = rel;
     }
     __syncthreads();
-    for (int k = tid; k < TILE; k += WG)
-      if (sS[k] < len && sS[k + 1] >= len) s_R = (uint32_t)k + 1;  // exactly one k
-    __syncthreads();
-    const uint32_t R = s_R, lead = s_lead;
+    const uint32_t lead = s_lead;
     if (stage_in && a.pack_in) {
       // packed rows: ceil(i*b/32) words each, column j in bits [j*b, j*b+b)
       const uint32_t b = (uint32_t)a.pack_bits, nw = (uint32_t)((i * b + 31) / 32);
