@@ -567,6 +567,7 @@ gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t 
       gsm::device_alloc((void **)&g->heavy, heavy.size() * sizeof(int32_t));
       GSM_HIP(hipMemcpy(g->heavy, heavy.data(), heavy.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
+    std::vector<int32_t> slot;  // bitmap index of each vertex, or -1 (empty: no bitmaps)
     if (!(flags & GSM_GRAPH_NO_HUB_BITMAPS) && n > 0) {
       // adjacency bitmaps of the highest-degree vertices, while they fit
       const uint64_t words = ((uint64_t)n + 31) / 32;
@@ -582,10 +583,8 @@ gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t 
       });
       if (hubs.size() > fit) hubs.resize(fit);
       if (!hubs.empty()) {
-        std::vector<int32_t> slot((size_t)n, -1);
+        slot.assign((size_t)n, -1);
         for (size_t k = 0; k < hubs.size(); ++k) slot[hubs[k]] = (int32_t)k;
-        gsm::device_alloc((void **)&g->hub_slot, (size_t)n * sizeof(int32_t));
-        GSM_HIP(hipMemcpy(g->hub_slot, slot.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice));
         gsm::device_alloc((void **)&g->hub_bits, hubs.size() * words * 4);
         GSM_HIP(hipMemset(g->hub_bits, 0, hubs.size() * words * 4));
         int32_t *d_hubs = nullptr;
@@ -606,6 +605,18 @@ gsm_status gsm_graph_create_ex(int64_t n, const int64_t *row_ptr, const int32_t 
         (void)hipFree(d_hubs);
         if (e != hipSuccess) throw Error{GSM_E_DEVICE, std::string("hub bitmaps: ") + hipGetErrorString(e)};
       }
+    }
+    if (n > 0) {
+      // one 16-byte record per vertex for the edge checks: list start (two
+      // halves), length, bitmap index or -1
+      std::vector<int4> vd((size_t)n);
+      for (int64_t v = 0; v < n; ++v) {
+        const uint64_t b = (uint64_t)h_rp[v];
+        vd[v] = make_int4((int32_t)(uint32_t)b, (int32_t)(uint32_t)(b >> 32), (int32_t)(h_rp[v + 1] - h_rp[v]),
+                          slot.empty() ? -1 : slot[v]);
+      }
+      gsm::device_alloc((void **)&g->vdesc, (size_t)n * sizeof(int4));
+      GSM_HIP(hipMemcpy(g->vdesc, vd.data(), (size_t)n * sizeof(int4), hipMemcpyHostToDevice));
     }
     if (reorder) {
       gsm::device_alloc((void **)&g->orig, (size_t)n * sizeof(int32_t));
@@ -633,7 +644,7 @@ void gsm_graph_destroy(gsm_graph_t g) {
   (void)hipFree(g->dne);
   (void)hipFree(g->ne0);
   (void)hipFree(g->heavy);
-  (void)hipFree(g->hub_slot);
+  (void)hipFree(g->vdesc);
   (void)hipFree(g->hub_bits);
   (void)hipFree(g->lab_vert);
   (void)hipFree(g->orig);

@@ -90,9 +90,10 @@ struct gsm_graph {
   int32_t *heavy = nullptr;  // vertices with degree > kHeavyDegree
   int64_t nheavy = 0;
   // adjacency bitmaps of the highest-degree vertices (membership in one load):
-  // hub_slot[v] = bitmap index of v or -1; bitmap s is hub_words 32-bit words
-  // at hub_bits + s * hub_words, bit w set when w is a neighbour
-  int32_t *hub_slot = nullptr;
+  // bitmap s is hub_words 32-bit words at hub_bits + s * hub_words, bit w set
+  // when w is a neighbour; vdesc[v] = (list start low, high, length, bitmap
+  // index or -1), the one load an edge check starts with
+  int4 *vdesc = nullptr;
   uint32_t *hub_bits = nullptr;
   uint64_t hub_words = 0;
   int64_t nhubs = 0;
@@ -239,7 +240,7 @@ struct DeviceGraph {
   int64_t n;
   const int32_t *elab;         // edge label per col entry, or null (every edge has label 0)
   const int32_t *elab_gather;  // edge label per gather entry, or null
-  const int32_t *hub_slot;     // bitmap index per vertex (-1: none), or null
+  const int4 *vdesc;           // per vertex: list start (low, high), length, bitmap index or -1
   const uint32_t *hub_bits;
   uint64_t hub_words;
   const int32_t *lab_vert;     // vertices sorted by label, or null
@@ -259,7 +260,7 @@ void launch_compact_first(const DeviceGraph &g, const uint16_t *cmask, uint32_t 
                           uint8_t *apos, uint64_t *counter, int32_t *emit_rows, uint64_t emit_cap,
                           hipStream_t s);
 void build_label_table(gsm_graph &g, const int64_t *h_rp, const int32_t *h_col, const int32_t *h_lab);
-// Adjacency bitmaps of the listed vertices (hub_slot, hub_bits already
+// Adjacency bitmaps of the listed vertices (hub_bits already
 // allocated and hub_bits zeroed): bitmap s gets the neighbours of hubs[s].
 void launch_build_hub_bitmaps(const gsm_graph &g, const int32_t *hubs, int64_t nhubs, hipStream_t s);
 // The device view of a graph.

@@ -86,21 +86,26 @@ __device__ __forceinline__ uint32_t search_steps(uint32_t n) {
   return n > 1 ? 33 - __builtin_clz(n - 1) : 1;
 }
 
+__device__ __forceinline__ int64_t vd_start(const int4 &d) {
+  return (int64_t)(((uint64_t)(uint32_t)d.y << 32) | (uint32_t)d.x);
+}
+
+// Is w a neighbour of x: one 16-byte record load, then one bitmap word or a
+// search of the sorted list.
 __device__ __forceinline__ bool has_edge(const DeviceGraph &g, int32_t x, int32_t w,
                                          uint32_t &probes) {
-  const int64_t b = g.rp[x];
-  const uint32_t n = (uint32_t)(g.rp[x + 1] - b);
+  const int4 d = g.vdesc[x];
+  const uint32_t n = (uint32_t)d.z;
   probes += search_steps(n);
-  // only lists of at least kHubMinDegree entries can have a bitmap
-  const int32_t hs = (g.hub_slot && n >= (uint32_t)kHubMinDegree) ? g.hub_slot[x] : -1;
-  if (hs >= 0) return (g.hub_bits[(uint64_t)hs * g.hub_words + ((uint32_t)w >> 5)] >> (w & 31)) & 1u;
-  return find_sorted(g.col + b, n, w) >= 0;
+  if (d.w >= 0) return (g.hub_bits[(uint64_t)d.w * g.hub_words + ((uint32_t)w >> 5)] >> (w & 31)) & 1u;
+  return find_sorted(g.col + vd_start(d), n, w) >= 0;
 }
 
 // Position of w in the sorted neighbour list of x (an index into col), or -1.
 __device__ __forceinline__ int64_t edge_pos(const DeviceGraph &g, int32_t x, int32_t w, uint32_t &probes) {
-  const int64_t b = g.rp[x];
-  const uint32_t n = (uint32_t)(g.rp[x + 1] - b);
+  const int4 d = g.vdesc[x];
+  const int64_t b = vd_start(d);
+  const uint32_t n = (uint32_t)d.z;
   probes += search_steps(n);
   const int32_t k = find_sorted(g.col + b, n, w);
   return k >= 0 ? b + k : -1;
@@ -261,7 +266,8 @@ __device__ __forceinline__ int32_t unpack_id(const uint32_t *row, uint32_t j, ui
 // Neighbour range of x that holds label l: [base, base + size) in g.gather.
 __device__ __forceinline__ uint32_t label_range(const DeviceGraph &g, int32_t x, int32_t l,
                                                 int64_t &base) {
-  const int64_t b = g.rp[x];
+  const int4 d = g.vdesc[x];
+  const int64_t b = vd_start(d);
   if (g.loff) {
     const uint32_t *o = g.loff + (int64_t)x * g.loff_stride;
     if (l + 1 >= g.loff_stride) {  // label absent from the graph
@@ -273,7 +279,7 @@ __device__ __forceinline__ uint32_t label_range(const DeviceGraph &g, int32_t x,
     return hi - lo;
   }
   base = b;
-  return g.deg[x];
+  return (uint32_t)d.z;
 }
 
 // k-look-ahead (Sec. 3.3) on a new row: the ids row[0..i) already matched
@@ -1136,7 +1142,7 @@ DeviceGraph device_graph(const gsm_graph &g) {
   return DeviceGraph{g.rp,     g.col,      g.lab,         g.deg,  g.ne0,
                      g.dne,    g.col_lab ? g.col_lab : g.col,     g.loff, g.loff_stride,
                      g.n,      g.elab,     g.elab_lab ? g.elab_lab : g.elab,
-                     g.hub_slot, g.hub_bits, g.hub_words, g.lab_vert, g.orig};
+                     g.vdesc, g.hub_bits, g.hub_words, g.lab_vert, g.orig};
 }
 
 void launch_filter_init(const DeviceGraph &g, const QueryArgs &qa, uint16_t *cmask, hipStream_t s) {
