@@ -341,6 +341,8 @@ struct ExpandArgs {
   uint32_t stage_limit;  // LDS bytes for staging rows (0 = kExpandStageBytes)
   int32_t staged;        // output rows pass through LDS (dynamic shared memory)
   int32_t stage_in;      // the tile's input rows are copied to LDS
+  uint32_t in_cap;       // rows the input staging holds (set by the launcher)
+  uint64_t level_pairs;  // pairs of the whole level (0: unknown), sizes in_cap
   int32_t stage_out_ok;  // the caller allows output staging
   LevelArgs L;
 };

@@ -528,6 +528,19 @@ __global__ __launch_bounds__(kScanWG) void k_scan_down(const uint32_t *W, const 
 // they fit.
 // EXT: edge labels or induced semantics are in force (a separate
 // instantiation, so the common one carries none of their registers).
+// Column j of a tile's input row: from the LDS copy when the tile staged its
+// rows, else from global memory (the empty asm keeps the two loads apart, so
+// the LDS one is not turned into a generic-address load).
+__device__ __forceinline__ int32_t row_id(bool staged, const int32_t *s_in, const int32_t *g, uint32_t li,
+                                          uint64_t gi) {
+  if (staged) {
+    int32_t x = s_in[li];
+    __asm__ volatile("" : "+v"(x));
+    return x;
+  }
+  return g[gi];
+}
+
 template <int WG, int ITEMS, int MODE, bool EXT>
 __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
   constexpr bool BATCHED = (MODE == kModeBatch || MODE == kModeBatchLast);
@@ -543,9 +556,11 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int i = a.L.i;
   const int width = (MODE == kModeNext || MODE == kModeBatch) ? i + 1 : a.L.q;
-  const bool stage_in = a.stage_in != 0;
+  // input staging holds in_cap rows; a tile touching more rows reads them
+  // from global memory
+  const bool stage_rows = a.stage_in != 0;
   int32_t *s_in = dyn;
-  int32_t *s_out = dyn + (stage_in ? TILE * i : 0);
+  int32_t *s_out = dyn + (stage_rows ? a.in_cap * (uint32_t)i : 0u);
   // rows and pair range: from the arguments, or (device-driven launches) the
   // level's row count and scan total as the previous kernels left them in
   // device memory, the range then clamped to the capacity the host gave; a
@@ -607,6 +622,7 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
     __syncthreads();
     const uint64_t r0 = s_r0;
     const uint32_t R = s_R;
+    const bool stage_in = stage_rows && R <= a.in_cap;  // uniform over the workgroup
     // row starts relative to the tile: sS[k] <= t < sS[k+1] for the pairs t
     // of row r0+k, k < R, and sS[R] >= len
     for (uint32_t k = tid; k <= R; k += WG) {
@@ -742,13 +758,12 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
         const uint32_t inj = ((1u << i) - 1u) & ~p_nbr[it];
         for (uint32_t m = inj; m; m &= m - 1) {
           const int j = __builtin_ctz(m);
-          const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
-          keep = keep && (x != w);
+          keep = keep && (row_id(stage_in, s_in, a.rows_in, k * i + j, (r0 + k) * i + j) != w);
         }
         // unique-subgraph mode: id order against symmetric earlier positions
         for (uint32_t m = a.L.sym_lt | a.L.sym_gt; m; m &= m - 1) {
           const int j = __builtin_ctz(m);
-          const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
+          const int32_t x = row_id(stage_in, s_in, a.rows_in, k * i + j, (r0 + k) * i + j);
           keep = keep && (((a.L.sym_lt >> j) & 1) ? x < w : x > w);
         }
         // edge labels: the anchor edge, then each back-edge below
@@ -757,7 +772,7 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
         for (uint32_t m = p_nbr[it]; m; m &= m - 1) {
           const int j = __builtin_ctz(m);
           if (keep && j != ap[it]) {
-            const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
+            const int32_t x = row_id(stage_in, s_in, a.rows_in, k * i + j, (r0 + k) * i + j);
             if (EXT && a.L.use_elab) {
               const int64_t pos = edge_pos(a.g, x, w, probes);
               keep = pos >= 0 && (a.g.elab ? a.g.elab[pos] : 0) == a.L.elab_req[j];
@@ -770,7 +785,7 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
         for (uint32_t m = EXT ? a.L.non_mask : 0u; m; m &= m - 1) {
           const int j = __builtin_ctz(m);
           if (keep) {
-            const int32_t x = stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j];
+            const int32_t x = row_id(stage_in, s_in, a.rows_in, k * i + j, (r0 + k) * i + j);
             keep = !has_edge(a.g, x, w, probes);
           }
         }
@@ -784,7 +799,7 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
           int64_t bb = 0;
           for (uint32_t mm = p_next_nbr[it]; mm; mm &= mm - 1) {
             const int j = __builtin_ctz(mm);
-            const int32_t x = (j == i) ? w : (stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j]);
+            const int32_t x = (j == i) ? w : (row_id(stage_in, s_in, a.rows_in, k * i + j, (r0 + k) * i + j));
             int64_t base;
             const uint32_t d = label_range(a.g, x, p_next_label[it], base);
             if (d < best) {
@@ -800,7 +815,7 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
             int64_t lo = -1, hi = (int64_t)1 << 31;
             for (uint32_t mm = a.L.next_sym_lt | a.L.next_sym_gt; mm; mm &= mm - 1) {
               const int j = __builtin_ctz(mm);
-              const int32_t x = (j == i) ? w : (stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j]);
+              const int32_t x = (j == i) ? w : (row_id(stage_in, s_in, a.rows_in, k * i + j, (r0 + k) * i + j));
               if ((a.L.next_sym_lt >> j) & 1)
                 lo = max(lo, (int64_t)x);
               else
@@ -946,33 +961,36 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
                   const int32_t lo = c * (int32_t)b - 32 * (int32_t)d;  // column start relative to the word
                   if (lo >= 32 || lo + (int32_t)b <= 0) continue;
                   const uint32_t v =
-                      (uint32_t)(c == i ? w : (stage_in ? s_in[k * i + c] : a.rows_in[(r0 + k) * i + c]));
+                      (uint32_t)(c == i ? w : (row_id(stage_in, s_in, a.rows_in, k * i + c, (r0 + k) * i + c)));
                   word |= lo >= 0 ? v << lo : v >> -lo;
                 }
                 o32[d] = word;
               }
               continue;
             }
+            // the row in output-column order (emitted rows carry the
+            // caller's ids on a renumbered graph)
+            auto colval = [&](int c) -> int32_t {
+              const int j = kIdOrder ? c : a.L.in_pos[c];
+              const int32_t x = j == i ? w : row_id(stage_in, s_in, a.rows_in, k * i + j, (r0 + k) * i + j);
+              return (!kIdOrder && a.g.orig) ? a.g.orig[x] : x;
+            };
+            if (a.staged) {  // into the LDS copy of the tile's rows
+              int32_t *o = s_out + loc * (uint32_t)width;
+              for (int c = 0; c < width; ++c) o[c] = colval(c);
+              continue;
+            }
             int32_t *o;
-            if (a.staged) {
-              o = s_out + loc * (uint32_t)width;
-            } else if (kIdOrder) {
+            if (kIdOrder) {
               o = a.rows_out + pos * (uint64_t)width;
             } else {
               const uint64_t slot = pos - a.emit_base;
               if (slot >= a.emit_cap) continue;
               o = a.emit_rows + slot * (uint64_t)width;
             }
-            // the row in output-column order, two columns per 8-byte store
-            // when the row starts 8-byte aligned (global rows only)
-            // (emitted rows carry the caller's ids on a renumbered graph)
-            auto colval = [&](int c) -> int32_t {
-              const int j = kIdOrder ? c : a.L.in_pos[c];
-              const int32_t x = j == i ? w : (stage_in ? s_in[k * i + j] : a.rows_in[(r0 + k) * i + j]);
-              return (!kIdOrder && a.g.orig) ? a.g.orig[x] : x;
-            };
+            // two columns per 8-byte store when the row starts 8-byte aligned
             int c = 0;
-            if (!a.staged && ((uintptr_t)o & 7) == 0) {
+            if (((uintptr_t)o & 7) == 0) {
               for (; c + 1 < width; c += 2)
                 *reinterpret_cast<int2 *>(o + c) = make_int2(colval(c), colval(c + 1));
             }
@@ -1061,10 +1079,23 @@ void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
   if (grid > kMaxGrid) grid = kMaxGrid;
   if (grid >= 8) grid &= ~7ull;
   const int width = (mode == kModeNext || mode == kModeBatch) ? a.L.i + 1 : a.L.q;
-  const size_t in_bytes = TILE * (size_t)a.L.i * sizeof(int32_t);
+  // input staging: room for every row a tile can touch, or, when the level's
+  // rows and pairs are known, 16 times the rows an average tile touches
+  // (rounded up to a power of two, at least 64): the rare tile with more rows
+  // reads them from global memory, and the LDS saved admits more workgroups
+  uint64_t in_cap = TILE;
+  if (a.level_pairs && !a.pack_in && !a.dev_pair_end) {
+    const uint64_t est = TILE * a.n_rows / a.level_pairs + 2;
+    uint64_t c = 64;
+    while (c < 16 * est && c < TILE) c <<= 1;
+    in_cap = std::min<uint64_t>(c, TILE);
+  }
+  a.in_cap = (uint32_t)in_cap;
+  const size_t in_bytes = in_cap * (size_t)a.L.i * sizeof(int32_t);
   const size_t out_bytes = TILE * (size_t)width * sizeof(int32_t);
   const size_t stage_max = a.stage_limit ? a.stage_limit : kMaxStageBytes;
   a.stage_in = (in_bytes <= stage_max) ? 1 : 0;
+  if (!a.stage_in) a.in_cap = 0;
   if (a.pack_in && !a.stage_in) throw Error{GSM_E_DEVICE, "packed frontier rows need staging"};
   if ((a.pack_in || a.pack_out) && (mode == kModeBatch || mode == kModeBatchLast))
     throw Error{GSM_E_DEVICE, "packed frontier rows in a batched launch"};

@@ -442,6 +442,7 @@ struct Matcher {
   // buffer, or chunks through the staging buffer to the host.
   void last_level(int i, uint64_t N, uint64_t P) {
     ExpandArgs a = level_expand_args(i, N);
+    a.level_pairs = P;
     a.counter = dcnt + kCntResult;
     if (!rows_user && !o.emit) {  // count only
       a.pair_begin = 0;
@@ -503,6 +504,7 @@ struct Matcher {
     const uint64_t b = f.b, e = std::min(f.P, b + cap[i + 1]);
     f.b = e;
     ExpandArgs a = level_expand_args(i, f.N);
+    a.level_pairs = f.P;
     reserve_level(i + 1, e - b);
     zero_counter(kCntRows + i + 1);
     a.pair_begin = b;
