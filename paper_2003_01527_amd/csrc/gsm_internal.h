@@ -144,6 +144,9 @@ constexpr int64_t kHeavyDegree = 2048;
 constexpr int64_t kHubMinDegree = 512;
 constexpr uint64_t kHubBitmapBytes = uint64_t(8) << 30;
 constexpr int32_t kMaxTableLabels = 64;
+// Tiles a host-driven expansion launch may map before it starts (8 bytes
+// each); larger launches search for their rows in the kernel.
+constexpr uint64_t kTileMapWords = uint64_t(1) << 20;
 
 // ------------------------------------------------------------------- plan --
 
@@ -344,6 +347,12 @@ struct ExpandArgs {
   uint32_t in_cap;       // rows the input staging holds (set by the launcher)
   uint64_t level_pairs;  // pairs of the whole level (0: unknown), sizes in_cap
   int32_t stage_out_ok;  // the caller allows output staging
+  // host-driven launches: a buffer of tile_map_cap words the launcher fills,
+  // before the expansion, with each tile's first row and row count (a tile
+  // then reads one word instead of searching S); 0 = search in the kernel
+  uint64_t *tile_map;
+  uint64_t tile_map_cap;
+  int32_t use_tile_map;  // set by the launcher
   LevelArgs L;
 };
 
@@ -453,6 +462,7 @@ struct Workspace {
   DevBuf counters;  // kMaxQ + 8 uint64
   DevBuf scan_scratch;
   DevBuf emit;      // staging for host-bound rows
+  DevBuf tilemap;   // expansion tile map (kTileMapWords words)
   uint64_t *h_counters = nullptr;  // pinned host mirror (a plain host array in a fixed workspace)
   std::vector<hipEvent_t> events;  // profiling event pool
   // Fixed workspace (no device allocation): every buffer is a window of

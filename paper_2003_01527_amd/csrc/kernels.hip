@@ -587,6 +587,13 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
   for (uint64_t tile = lb; tile < ntiles; tile += G) {
     const uint64_t t0 = a.pair_begin + tile * TILE;
     const uint32_t len = (uint32_t)min((uint64_t)TILE, pair_end - t0);
+    uint64_t r0;
+    uint32_t R;
+    if (a.use_tile_map) {  // first row and row count, found before the launch
+      const uint64_t e = a.tile_map[tile];
+      r0 = e & ((uint64_t(1) << 48) - 1);
+      R = (uint32_t)(e >> 48);
+    } else {
     if (wid == 0) {
       // 64-way search by the first wave: S[lo] <= t0 < S[hi]; every round
       // shrinks the interval 64-fold (5 dependent loads for 10^8 rows).
@@ -620,8 +627,9 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
       }
     }
     __syncthreads();
-    const uint64_t r0 = s_r0;
-    const uint32_t R = s_R;
+    r0 = s_r0;
+    R = s_R;
+    }
     const bool stage_in = stage_rows && R <= a.in_cap;  // uniform over the workgroup
     // row starts relative to the tile: sS[k] <= t < sS[k+1] for the pairs t
     // of row r0+k, k < R, and sS[R] >= len
@@ -1059,12 +1067,44 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
   }
 }
 
+// The expansion's tile map: for tile t of [pair_begin, pair_end), the last
+// row r0 with S[r0] <= t0 and the number R of rows the tile touches (every
+// row has at least one pair, so they end within len rows of r0), packed as
+// r0 | R << 48; one thread per tile, two binary searches.
+__global__ void k_tile_rows(const uint64_t *__restrict__ S, uint64_t n_rows, uint64_t pair_begin,
+                            uint64_t pair_end, uint32_t tile, uint64_t ntiles, uint64_t *map) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += stride) {
+    const uint64_t t0 = pair_begin + t * tile;
+    const uint64_t e = min(t0 + tile, pair_end);
+    uint64_t lo = 0, hi = n_rows;  // S[lo] <= t0 < S[hi]
+    while (hi - lo > 1) {
+      const uint64_t mid = lo + (hi - lo) / 2;
+      if (S[mid] <= t0)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    uint64_t lo2 = lo, hi2 = min(n_rows, lo + (e - t0));  // S[lo2] < e <= S[hi2]
+    while (hi2 - lo2 > 1) {
+      const uint64_t mid = lo2 + (hi2 - lo2) / 2;
+      if (S[mid] < e)
+        lo2 = mid;
+      else
+        hi2 = mid;
+    }
+    map[t] = lo | ((hi2 - lo) << 48);
+  }
+}
+
 __global__ void k_zero_u64(uint64_t *p, size_t count) {
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x)
     p[k] = 0;
 }
 
 constexpr size_t kMaxStageBytes = kExpandStageBytes;
+
+uint32_t grid_for(int64_t work, int wg, uint32_t cap);
 
 template <int WG, int ITEMS>
 void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
@@ -1091,6 +1131,13 @@ void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
     in_cap = std::min<uint64_t>(c, TILE);
   }
   a.in_cap = (uint32_t)in_cap;
+  a.use_tile_map = 0;
+  if (a.tile_map && !a.dev_pair_end && ntiles <= a.tile_map_cap && a.n_rows > 0) {
+    hipLaunchKernelGGL(k_tile_rows, dim3(grid_for((int64_t)ntiles, 256, 4096)), dim3(256), 0, s, a.S, a.n_rows,
+                       a.pair_begin, a.pair_end, (uint32_t)TILE, ntiles, a.tile_map);
+    GSM_HIP(hipGetLastError());
+    a.use_tile_map = 1;
+  }
   const size_t in_bytes = in_cap * (size_t)a.L.i * sizeof(int32_t);
   const size_t out_bytes = TILE * (size_t)width * sizeof(int32_t);
   const size_t stage_max = a.stage_limit ? a.stage_limit : kMaxStageBytes;

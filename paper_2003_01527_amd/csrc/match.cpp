@@ -212,6 +212,11 @@ struct Matcher {
     a.probes = dcnt + kCntProbes;
     a.stage_out_ok = o.stage_out;
     a.stage_limit = o.stage_bytes;
+    if (!ws.fixed_base) {  // (the no-allocation scratch has no room for the tile map)
+      ws.tilemap.reserve(kTileMapWords * sizeof(uint64_t), s);
+      a.tile_map = ws.tilemap.as<uint64_t>();
+      a.tile_map_cap = kTileMapWords;
+    }
     if (o.profile) {
       auto pr = next_events();
       GSM_HIP(hipEventRecord(pr.first, s));
@@ -240,7 +245,11 @@ struct Matcher {
       if (cap[i] < 1) throw Error{GSM_E_BUDGET, "memory budget below one row of level " + std::to_string(i)};
     }
     if (emit_host) {
-      staged_cap = std::min<uint64_t>(rest / shares / (uint64_t)(4 * p.q), uint64_t(1) << 26);
+      // pairs per output chunk (a chunk's rows fit the staging buffer); a
+      // device-side sink takes chunks of up to 2^30 pairs (fewer launches and
+      // hand-overs), a host-side one 2^26 (its host copy stays small)
+      const uint64_t chunk_max = (o.emit && o.rows_dev) ? uint64_t(1) << 30 : uint64_t(1) << 26;
+      staged_cap = std::min<uint64_t>(rest / shares / (uint64_t)(4 * p.q), chunk_max);
       if (staged_cap < 1) throw Error{GSM_E_BUDGET, "memory budget below one output row"};
     }
     if (ws.fixed_base) {
@@ -444,11 +453,15 @@ struct Matcher {
     ExpandArgs a = level_expand_args(i, N);
     a.level_pairs = P;
     a.counter = dcnt + kCntResult;
-    if (!rows_user && !o.emit) {  // count only
-      a.pair_begin = 0;
-      a.pair_end = P;
-      expand(a, kModeCount);
-      st.chunks[i]++;
+    if (!rows_user && !o.emit) {  // count only, in launches of at most kTileMapWords tiles
+      const uint64_t tile = (uint64_t)(o.wg ? o.wg : 512) * (uint64_t)(o.items ? o.items : 4);
+      const uint64_t span = kTileMapWords * tile;
+      for (uint64_t b = 0; b < P; b += span) {
+        a.pair_begin = b;
+        a.pair_end = std::min(P, b + span);
+        expand(a, kModeCount);
+        st.chunks[i]++;
+      }
     } else if (!emit_host) {  // rows straight into the caller's device buffer
       a.pair_begin = 0;
       a.pair_end = P;
