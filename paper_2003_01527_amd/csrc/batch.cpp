@@ -82,6 +82,7 @@ struct BatchMatcher {
   // query slot nq: rows of evicted queries are retagged to it; every
   // candidate test fails there (no vertex has 2^32 - 1 neighbours)
   void upload_tables() {
+    if (!ws.fixed_base) ws.tilemap.reserve(kTileMapWords * sizeof(uint64_t), s);
     std::vector<BatchLevel> bl((size_t)(nq + 1) * kMaxQ);
     for (int i = 0; i < kMaxQ; ++i) {
       BatchLevel &e = bl[(size_t)nq * kMaxQ + i];
@@ -256,6 +257,8 @@ struct BatchMatcher {
     a.probes = dcnt + kCntProbes;
     a.stage_out_ok = 1;
     a.stage_limit = stage_bytes;
+    a.tile_map = ws.tilemap.as<uint64_t>();
+    a.tile_map_cap = a.tile_map ? kTileMapWords : 0;
     return a;
   }
 
@@ -401,7 +404,8 @@ struct BatchMatcher {
     put(&items, sizeof(items));
     put(&evict_pairs, sizeof(evict_pairs));
     put(&stage_bytes, sizeof(stage_bytes));
-    const void *ptrs[] = {d_bl, d_fb, d_counts, dcnt, ws.scan_scratch.ptr, ws.qpairs.ptr, ws.evicted.ptr};
+    const void *ptrs[] = {d_bl, d_fb, d_counts, dcnt, ws.scan_scratch.ptr, ws.qpairs.ptr, ws.evicted.ptr,
+                          ws.tilemap.ptr};
     put(ptrs, sizeof(ptrs));
     for (int i = 1; i <= maxq && i < kMaxQ; ++i) {
       const void *lv[] = {ws.rows[i].ptr, ws.W[i].ptr, ws.apos[i].ptr, ws.abase[i].ptr, ws.S[i].ptr, ws.qid[i].ptr};

@@ -347,9 +347,9 @@ struct ExpandArgs {
   uint32_t in_cap;       // rows the input staging holds (set by the launcher)
   uint64_t level_pairs;  // pairs of the whole level (0: unknown), sizes in_cap
   int32_t stage_out_ok;  // the caller allows output staging
-  // host-driven launches: a buffer of tile_map_cap words the launcher fills,
-  // before the expansion, with each tile's first row and row count (a tile
-  // then reads one word instead of searching S); 0 = search in the kernel
+  // a buffer of tile_map_cap words the launcher fills, before the expansion,
+  // with the first row and row count of each of the first tile_map_cap tiles
+  // (such a tile reads one word instead of searching S); null = search
   uint64_t *tile_map;
   uint64_t tile_map_cap;
   int32_t use_tile_map;  // set by the launcher

@@ -589,7 +589,7 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
     const uint32_t len = (uint32_t)min((uint64_t)TILE, pair_end - t0);
     uint64_t r0;
     uint32_t R;
-    if (a.use_tile_map) {  // first row and row count, found before the launch
+    if (a.use_tile_map && tile < a.tile_map_cap) {  // first row and row count, found before the launch
       const uint64_t e = a.tile_map[tile];
       r0 = e & ((uint64_t(1) << 48) - 1);
       R = (uint32_t)(e >> 48);
@@ -1071,8 +1071,18 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
 // row r0 with S[r0] <= t0 and the number R of rows the tile touches (every
 // row has at least one pair, so they end within len rows of r0), packed as
 // r0 | R << 48; one thread per tile, two binary searches.
+// Device-driven launches: the row count and pair total are read from device
+// memory as the expansion reads them, and only the first `cap` tiles are
+// mapped (the expansion searches for the rest).
 __global__ void k_tile_rows(const uint64_t *__restrict__ S, uint64_t n_rows, uint64_t pair_begin,
-                            uint64_t pair_end, uint32_t tile, uint64_t ntiles, uint64_t *map) {
+                            uint64_t pair_end, uint32_t tile, const uint64_t *dev_n_rows,
+                            const uint64_t *dev_pair_end, uint64_t cap, uint64_t *map) {
+  if (dev_pair_end) {
+    n_rows = *dev_n_rows;
+    pair_end = min(pair_end, *dev_pair_end);
+  }
+  const uint64_t npairs = pair_end > pair_begin ? pair_end - pair_begin : 0;
+  const uint64_t ntiles = min((npairs + tile - 1) / tile, cap);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += stride) {
     const uint64_t t0 = pair_begin + t * tile;
@@ -1132,9 +1142,11 @@ void launch_expand_t(ExpandArgs a, int mode, hipStream_t s) {
   }
   a.in_cap = (uint32_t)in_cap;
   a.use_tile_map = 0;
-  if (a.tile_map && !a.dev_pair_end && ntiles <= a.tile_map_cap && a.n_rows > 0) {
-    hipLaunchKernelGGL(k_tile_rows, dim3(grid_for((int64_t)ntiles, 256, 4096)), dim3(256), 0, s, a.S, a.n_rows,
-                       a.pair_begin, a.pair_end, (uint32_t)TILE, ntiles, a.tile_map);
+  if (a.tile_map && a.tile_map_cap) {
+    const uint64_t mapped = std::min<uint64_t>(ntiles, a.tile_map_cap);
+    hipLaunchKernelGGL(k_tile_rows, dim3(grid_for((int64_t)mapped, 256, 4096)), dim3(256), 0, s, a.S, a.n_rows,
+                       a.pair_begin, a.pair_end, (uint32_t)TILE, a.dev_n_rows, a.dev_pair_end, a.tile_map_cap,
+                       a.tile_map);
     GSM_HIP(hipGetLastError());
     a.use_tile_map = 1;
   }
