@@ -644,8 +644,7 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
       }
       sS[k] = rel;
     }
-    __syncthreads();
-    const uint32_t lead = s_lead;
+    // the rows are copied in the same phase (one barrier for both)
     if (stage_in && a.pack_in) {
       // packed rows: ceil(i*b/32) words each, column j in bits [j*b, j*b+b)
       const uint32_t b = (uint32_t)a.pack_bits, nw = (uint32_t)((i * b + 31) / 32);
@@ -655,7 +654,8 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
       const int32_t *src = a.rows_in + r0 * (uint64_t)i;
       for (uint32_t e = tid; e < R * (uint32_t)i; e += WG) s_in[e] = src[e];
     }
-    if (stage_in) __syncthreads();
+    __syncthreads();
+    const uint32_t lead = s_lead;
 
     // ---- evaluation (no barriers): row, candidate, checks of every item
     uint32_t rk[ITEMS], off[ITEMS];
