@@ -713,10 +713,10 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
       int32_t p_next_label[ITEMS];
       bool cand[ITEMS];
       if (BATCHED) {
-        BatchLevel bl[ITEMS];
-#pragma unroll
-        for (int it = 0; it < ITEMS; ++it) bl[it] = UNI ? ubl : a.blev[qk[it] * kMaxQ + i];
-        // candidate test: every item's load issued before any is used
+        // candidate test: every item's graph loads issued before any is used;
+        // the level entries are read field by field where they are needed
+        // (a wave whose items span queries reads them per item, so they do
+        // not all stay in registers)
         uint2 dn[ITEMS];
         int32_t lv[ITEMS];
         const bool label_known = a.g.loff != nullptr;
@@ -727,14 +727,18 @@ __global__ __launch_bounds__(WG) void k_expand(ExpandArgs a) {
         }
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
-          p_nbr[it] = bl[it].nbr_mask;
-          p_next_nbr[it] = bl[it].next_nbr_mask;
-          p_next_label[it] = bl[it].next_label;
+          const BatchLevel *bp = a.blev + (qk[it] * kMaxQ + i);
+          p_nbr[it] = UNI ? ubl.nbr_mask : bp->nbr_mask;
+          p_next_nbr[it] = UNI ? ubl.next_nbr_mask : bp->next_nbr_mask;
+          p_next_label[it] = UNI ? ubl.next_label : bp->next_label;
           p_last[it] = (MODE == kModeBatchLast);
-          cand[it] = dn[it].x >= bl[it].qdeg && (uint64_t)dn[it].y >= bl[it].qne &&
-                     (label_known || lv[it] == bl[it].qlab);
-          if (bl[it].slice_mod && cand[it])
-            cand[it] = slice_mix(slice_id(a.g, wv[it])) % bl[it].slice_mod == bl[it].slice_rem;
+          const uint32_t qdeg = UNI ? ubl.qdeg : bp->qdeg;
+          const uint64_t qne = UNI ? ubl.qne : bp->qne;
+          const int32_t qlab = UNI ? ubl.qlab : bp->qlab;
+          const uint32_t smod = UNI ? ubl.slice_mod : bp->slice_mod;
+          cand[it] = dn[it].x >= qdeg && (uint64_t)dn[it].y >= qne && (label_known || lv[it] == qlab);
+          if (smod && cand[it])
+            cand[it] = slice_mix(slice_id(a.g, wv[it])) % smod == (UNI ? ubl.slice_rem : bp->slice_rem);
         }
       } else {
         uint32_t cm[ITEMS];
