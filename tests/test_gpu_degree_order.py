@@ -223,3 +223,33 @@ def test_bad_ids_rejected_degree_order():
         gsm.Graph(np.array([0, 2, 1], np.int64), np.array([1, 0], np.int32), degree_order=True)
     G = gsm.Graph(np.zeros(1, np.int64), np.zeros(0, np.int32), degree_order=True)  # no vertices
     assert G.info()["n"] == 0
+
+
+def test_device_pointers_and_strip_with_degree_order():
+    # the renumbering also takes CSR arrays in device memory, and a cleaned
+    # (stripped) adjacency; rows stay in the caller's ids
+    g = W.rmat_graph(10, 5, 0.57, 0.19, 0.19, 91)
+    g = W.Graph(g.row_ptr, g.col, W.labels_zipf(g.n, 3, 1.0, 4), "labelled")
+    qr = W.random_query(4, 0.5, 3, 17)
+    Q = gsm.Query.from_workload(qr)
+    c, r = oracle.match(g, qr)
+    dev = lambda a, dt: torch.tensor(np.asarray(a), dtype=dt, device="cuda:0")
+    G = gsm.Graph(dev(g.row_ptr, torch.int64), dev(g.col, torch.int32), dev(g.labels, torch.int32),
+                  degree_order=True)
+    cg, rg = gpu_sorted(G, Q)
+    assert cg == c
+    np.testing.assert_array_equal(rg, r)
+    # the same adjacency with every edge stored once and a self-loop added:
+    # GSM_GRAPH_STRIP rebuilds it before the renumbering
+    n = g.n
+    src = np.repeat(np.arange(n), np.diff(g.row_ptr))
+    keep = src < g.col
+    half_src, half_dst = np.append(src[keep], 0), np.append(g.col[keep], 0)
+    order = np.argsort(half_src, kind="stable")
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, half_src[order] + 1, 1)
+    rp = np.cumsum(rp)
+    G2 = gsm.Graph(rp, half_dst[order].astype(np.int32), g.labels, strip=True, degree_order=True)
+    cg2, rg2 = gpu_sorted(G2, Q)
+    assert cg2 == c
+    np.testing.assert_array_equal(rg2, r)
