@@ -519,10 +519,11 @@ __global__ __launch_bounds__(kScanWG) void k_scan_down(const uint32_t *W, const 
 // binary search for every other back-edge; when the row goes on to a further
 // level it must also leave a non-empty range for the next query vertex.
 //
-// Per tile: the first wave finds the tile's first row by a 64-way search; the
-// rows the tile touches are copied to LDS with contiguous loads; every item's
-// loads are issued before any result is used, so a wave keeps ITEMS gathers
-// in flight.  Survivors are compacted item by item (wave ballot, workgroup
+// Per tile: the first row and the number of rows come from the launch's tile
+// map (or, past its end or without one, from two 64-way searches by the
+// first wave); the rows the tile touches are copied to LDS with contiguous
+// loads; every item's loads are issued before any result is used, so a wave
+// keeps ITEMS gathers in flight.  Survivors are compacted item by item (wave ballot, workgroup
 // prefix, one atomic per tile) so consecutive lanes write consecutive rows;
 // output rows are staged in LDS and copied out with contiguous stores when
 // they fit.
